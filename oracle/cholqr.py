@@ -1,0 +1,202 @@
+"""Oracle algorithms: CholeskyQR, CholeskyQR2, CQRGS, CQR2GS and mCQR2GS.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring). Plain FP64 NumPy/SciPy,
+one step per line of the paper's algorithms, no blocking or fusion beyond
+what the algorithms state. Library primitives used as steps: BLAS matrix
+products, LAPACK ``dpotrf`` (Cholesky with its breakdown index) and
+``dtrsm`` through ``scipy.linalg.solve_triangular``.
+
+Readings of the paper where it is silent:
+* Summation over m is chunked: every Gram matrix and every projection is the
+  sum of per-chunk products over CHUNK-row blocks, added in a fixed pairwise
+  tree. The paper is silent on accumulation order; this bounds the rounding
+  depth at m = 2^22 the same way the parallel algorithm's per-rank partial
+  sums do (section "CholeskyQR", Algorithm 2; Algorithm 8).
+* A Cholesky breakdown (non-positive or NaN pivot) raises ``Breakdown`` with
+  the 1-based global column of the failing pivot; the paper only says the
+  algorithm fails there (sections "CholeskyQR" and "CholeskyQR2").
+* The second CQRGS pass of CQR2GS uses the same panel width as the first.
+* mCQR2GS (Algorithm 9) leaves R implicit; R is assembled as derived in
+  ``mcqr2gs``.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+from scipy.linalg import lapack
+
+CHUNK = 4096
+
+
+class Breakdown(ArithmeticError):
+    """Cholesky of a Gram matrix met a pivot that is not > 0 (or is NaN)."""
+
+    def __init__(self, column: int):
+        super().__init__(f"Gram matrix not positive definite at column {column}")
+        self.column = column
+
+
+def _pairwise(parts):
+    """Fixed pairwise tree sum of a list of equally shaped arrays."""
+    while len(parts) > 1:
+        nxt = [parts[i] + parts[i + 1] for i in range(0, len(parts) - 1, 2)]
+        if len(parts) % 2:
+            nxt.append(parts[-1])
+        parts = nxt
+    return parts[0]
+
+
+def xprod(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """X^T Y summed over CHUNK-row blocks in a pairwise tree.
+
+    The local products and their sum are the Gram / projection steps of the
+    parallel algorithms (Algorithm 2 lines computing W_i and the Allreduce;
+    Algorithm 8 lines computing W_{p,j}, Y_p and their Allreduce), with row
+    chunks standing in for processors.
+    """
+    m = x.shape[0]
+    if m == 0:
+        return np.zeros((x.shape[1], y.shape[1]))
+    parts = [x[i:i + CHUNK].T @ y[i:i + CHUNK] for i in range(0, m, CHUNK)]
+    return _pairwise(parts)
+
+
+def gram(x: np.ndarray) -> np.ndarray:
+    """W = X^T X (Algorithm 1, Gram-matrix step), chunked as in ``xprod``."""
+    return xprod(x, x)
+
+
+def chol_upper(w: np.ndarray, col0: int = 0) -> np.ndarray:
+    """Upper Cholesky factor U with W = U^T U (Algorithm 1, Cholesky step).
+
+    Uses LAPACK dpotrf on the upper triangle; a failure raises Breakdown with
+    the 1-based global column col0 + info.
+    """
+    c, info = lapack.dpotrf(np.array(w, order="F", copy=True), lower=0, clean=1)
+    if info > 0:
+        raise Breakdown(col0 + int(info))
+    if info < 0:
+        raise ValueError("dpotrf argument error")
+    # some LAPACK builds let a NaN pivot through; a pivot that is not > 0
+    # (NaN included) is a breakdown at that column
+    bad = np.flatnonzero(~(np.diag(c) > 0))
+    if bad.size:
+        raise Breakdown(col0 + int(bad[0]) + 1)
+    return np.triu(c)
+
+
+def _right_solve_upper(x: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """X U^{-1} by triangular solve (Algorithm 1, Q := A R^{-1}, via trsm)."""
+    # solve U^T Z = X^T for Z = (X U^{-1})^T
+    return sla.solve_triangular(u, x.T, trans="T", lower=False, check_finite=False).T
+
+
+def cqr(x: np.ndarray, col0: int = 0):
+    """CholeskyQR, Algorithm 1 (its parallel form, Algorithm 2): returns Q, R."""
+    w = gram(x)
+    u = chol_upper(w, col0)
+    q = _right_solve_upper(x, u)
+    return q, u
+
+
+def cqr2(x: np.ndarray, col0: int = 0):
+    """CholeskyQR2, Algorithm 3: CQR twice, R = R2 R1."""
+    q1, r1 = cqr(x, col0)
+    q, r2 = cqr(q1, col0)
+    return q, r2 @ r1
+
+
+def _panels(n: int, b: int):
+    if b < 1:
+        raise ValueError("panel width must be >= 1")
+    b = min(b, n)
+    return [(s, min(s + b, n)) for s in range(0, n, b)]
+
+
+def cqrgs(a: np.ndarray, b: int):
+    """CholeskyQR with block Gram-Schmidt, Algorithm 6 (distributed form:
+    Algorithm 8). Returns Q, R. A is not modified."""
+    m, n = a.shape
+    x = np.array(a, dtype=np.float64, order="F", copy=True)
+    r = np.zeros((n, n))
+    for (s, e) in _panels(n, b):
+        w = gram(x[:, s:e])                      # W_j := A_j^T A_j
+        u = chol_upper(w, s)                     # W_j = U^T U
+        x[:, s:e] = _right_solve_upper(x[:, s:e], u)   # Q_j := A_j U^{-1}
+        r[s:e, s:e] = u                          # R_jj := U
+        if e < n:
+            y = xprod(x[:, s:e], x[:, e:])       # Y := Q_j^T A_{j+1:k}
+            x[:, e:] -= x[:, s:e] @ y            # A_{j+1:k} -= Q_j Y
+            r[s:e, e:] = y                       # R_{j,j+1:k} := Y
+    return x, r
+
+
+def cqr2gs(a: np.ndarray, b: int):
+    """CholeskyQR2 with Gram-Schmidt (the paper's CQR2GS), Algorithm 7:
+    CQRGS twice with the same panel width, then R = R2 R1."""
+    q1, r1 = cqrgs(a, b)
+    q, r2 = cqrgs(q1, b)
+    return q, r2 @ r1
+
+
+def mcqr2gs(a: np.ndarray, b: int):
+    """Modified CholeskyQR2 with Gram-Schmidt (mCQR2GS), Algorithm 9.
+
+    Steps per panel j >= 2 (1-based as in the paper):
+      Y := Q_{j-1}^T A_{:,j:k};  A_{:,j:k} -= Q_{j-1} Y;  R_{j-1,j:k} := Y
+      CQR of panel j:     A_j = Qt Ua
+      re-orthogonalise:   Z := Q_{1:j-1}^T Qt;  Qt -= Q_{1:j-1} Z
+      CQR again:          Qt = Q_j Ub
+    so that A_j (after the Y updates) = Q_{1:j-1} (Z Ua) + Q_j (Ub Ua), which
+    gives R_{1:j-1,j} += Z Ua and R_jj = Ub Ua. The first panel is CQR2
+    (Algorithm 9, first line). The paper does not write R for this algorithm;
+    this is the bookkeeping that makes A = Q R hold.
+    """
+    m, n = a.shape
+    x = np.array(a, dtype=np.float64, order="F", copy=True)
+    r = np.zeros((n, n))
+    pan = _panels(n, b)
+    s0, e0 = pan[0]
+    x[:, s0:e0], r[s0:e0, s0:e0] = cqr2(x[:, s0:e0], s0)
+    for jj in range(1, len(pan)):
+        ps, pe = pan[jj - 1]
+        s, e = pan[jj]
+        y = xprod(x[:, ps:pe], x[:, s:])          # Y := Q_{j-1}^T A_{:,j:k}
+        x[:, s:] -= x[:, ps:pe] @ y               # A_{:,j:k} -= Q_{j-1} Y
+        r[ps:pe, s:] = y                          # R_{j-1,j:k} := Y
+        qt, ua = cqr(x[:, s:e], s)                # CQR(A_j)
+        z = xprod(x[:, :s], qt)                   # Q_{1:j-1}^T A_j
+        qt = qt - x[:, :s] @ z                    # A_j -= Q_{1:j-1} Q_{1:j-1}^T A_j
+        qj, ub = cqr(qt, s)                       # Q_j = CQR(A_j)
+        x[:, s:e] = qj
+        r[:s, s:e] += z @ ua
+        r[s:e, s:e] = ub @ ua
+    return x, r
+
+
+def householder_qr(a: np.ndarray):
+    """Independent reference: LAPACK Householder QR (dgeqrf/dorgqr) with the
+    sign normalisation that makes diag(R) > 0 (thin QR is then unique)."""
+    q, r = np.linalg.qr(a)
+    d = np.sign(np.diag(r))
+    d[d == 0] = 1.0
+    return q * d, d[:, None] * r
+
+
+def qr_adjoint(q: np.ndarray, r: np.ndarray, dq=None, dr=None) -> np.ndarray:
+    """Reverse-mode derivative of the thin QR map A -> (Q, R), m >= n.
+
+    dA = (dQ + Q copyltu(M)) R^{-T},  M = R dR^T - dQ^T Q,
+    copyltu(M) = tril(M) + tril(M, -1)^T (the lower triangle mirrored).
+    This is the published QR adjoint for full-column-rank A; the paper does
+    not differentiate the factorisation. The lower triangle of dR is ignored;
+    a missing cotangent counts as zero.
+    """
+    m, n = q.shape
+    dq = np.zeros((m, n)) if dq is None else np.asarray(dq)
+    dr = np.zeros((n, n)) if dr is None else np.triu(np.asarray(dr))
+    mm = r @ dr.T - xprod(dq, q)
+    c = np.tril(mm) + np.tril(mm, -1).T
+    g = dq + q @ c
+    # right-multiply by R^{-T}: solve Z R^T = G  <=>  R Z^T = G^T
+    return sla.solve_triangular(r, g.T, lower=False, check_finite=False).T

@@ -1,0 +1,136 @@
+/*
+ * libcqr: CholeskyQR2 with block Gram-Schmidt on AMD Instinct MI355X (gfx950).
+ *
+ * Thin QR factorisation A = Q R of a tall-and-skinny FP64 matrix (m >= n)
+ * by the two schedules of Mijic, Kaushik and Davidovic, "QR factorization of
+ * ill-conditioned tall-and-skinny matrices on distributed-memory systems"
+ * (arXiv 2405.04237):
+ *
+ *   CQR_SCHED_ORIG  CholeskyQR2 with Gram-Schmidt (CQR2GS): block
+ *                   Gram-Schmidt CholeskyQR (Algorithm 6, distributed form
+ *                   Algorithm 8) applied twice, R = R2 R1 (Algorithm 7).
+ *   CQR_SCHED_MOD   modified CQR2GS (mCQR2GS, Algorithm 9): CholeskyQR2 of the
+ *                   first panel, then per panel one projection/update against
+ *                   the previous (fully orthogonal) panel, CholeskyQR,
+ *                   re-orthogonalisation against all previous panels, and
+ *                   CholeskyQR again.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All matrices are FP64 and column-major (LAPACK layout). A and Q are m x n
+ *   with leading dimension lda >= max(1, m); R is n x n with leading
+ *   dimension n. All pointers are device pointers unless marked "host".
+ * - Panel j covers columns [j b, min((j+1) b, n)); the last panel may be
+ *   narrower. b = 0 selects a default width; b > n is clamped to n. After
+ *   clamping 1 <= b <= CQR_MAX_PANEL: the Cholesky factor and inverse of a
+ *   panel's b x b Gram matrix are formed in the local data share of one
+ *   workgroup (128 x 128 FP64 = 128 KiB of the 160 KiB a gfx950 workgroup
+ *   may hold); a wider b returns CQR_ERR_UNSUPPORTED.
+ * - A is only read. Q may equal A (in-place factorisation); any other
+ *   overlap of A, Q, R, the workspace or the info word is an error the
+ *   library does not detect.
+ * - On success R is upper triangular with a positive diagonal and an exactly
+ *   zero strict lower triangle.
+ * - Calls are asynchronous and ordered on `stream` (a hipStream_t; NULL is
+ *   the default stream). No entry point synchronises except cqr_get_info and
+ *   cqr_profile_query. Results are bitwise reproducible for fixed arguments.
+ * - Numerical breakdown is reported asynchronously through an info word in
+ *   device memory: 0 = success; j > 0 = the Gram matrix of a panel was not
+ *   numerically positive definite at global column j (1-based), i.e. a
+ *   Cholesky pivot was not > 0 or was NaN (the failure mode the paper names
+ *   in sections "CholeskyQR" and "CholeskyQR2"). Once set, the remaining
+ *   kernels of that factorisation do nothing and Q, R are undefined.
+ *   Nothing is shifted, retried or silently repaired.
+ * - Return values: CQR_OK, or a negative status (argument errors are
+ *   detected before any device work is queued).
+ */
+#ifndef LIBCQR_CQR_H
+#define LIBCQR_CQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum cqr_status {
+  CQR_OK = 0,
+  CQR_ERR_ARG = -1,         /* invalid argument; nothing was launched */
+  CQR_ERR_HIP = -2,         /* a HIP runtime call or kernel launch failed */
+  CQR_ERR_NOMEM = -3,       /* the library could not allocate its workspace */
+  CQR_ERR_WORKSPACE = -4,   /* caller workspace smaller than required */
+  CQR_ERR_UNSUPPORTED = -5  /* a size this build does not handle */
+};
+
+#define CQR_MAX_PANEL 128
+
+enum cqr_schedule {
+  CQR_SCHED_MOD = 0,   /* mCQR2GS, Algorithm 9 (default) */
+  CQR_SCHED_ORIG = 1   /* CQR2GS, Algorithm 7 */
+};
+
+typedef struct cqr_options {
+  int schedule;            /* enum cqr_schedule */
+  int *d_info;             /* device int for the breakdown column; NULL = the
+                              library's internal word (read by cqr_get_info) */
+  void *workspace;         /* device scratch of >= cqr_workspace_bytes(...)
+                              bytes, 256-byte aligned; NULL = a workspace the
+                              library allocates once per device and keeps */
+  size_t workspace_bytes;  /* size of `workspace` */
+} cqr_options;
+
+/* Factor A = Q R with the default schedule (mCQR2GS). Q has leading
+ * dimension lda, R leading dimension n. Uses the library's internal
+ * workspace and info word, so concurrent calls on different streams of one
+ * device must use cqr_factor_ex with their own workspace instead. */
+int cqr_factor(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
+               double *Q, double *R, void *stream);
+
+/* As cqr_factor, with the schedule, info word and workspace chosen by the
+ * caller (opt may be NULL for the defaults). */
+int cqr_factor_ex(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
+                  double *Q, double *R, void *stream, const cqr_options *opt);
+
+/* Bytes of device workspace cqr_factor_ex needs for these sizes (host
+ * arithmetic only; 0 for invalid sizes). The info word is not included. */
+size_t cqr_workspace_bytes(int64_t m, int64_t n, int64_t b, int schedule);
+
+/* Panel width used when b = 0 is passed. */
+int64_t cqr_default_panel(int64_t m, int64_t n, int schedule);
+
+/* Wait for `stream` and copy the library's internal info word of the current
+ * device into *info (host). */
+int cqr_get_info(void *stream, int *info);
+
+/* Human-readable text of a status code (static storage). */
+const char *cqr_status_string(int status);
+
+/* Per-kernel timing. While enabled, every kernel launch of the library is
+ * bracketed by HIP events on its stream and credited with its algorithmic
+ * flops and bytes (the paper's Table 1/2 counts: Gram m w^2, forming Q
+ * m w^2, projection and update 2 m p q each). cqr_profile_query waits for
+ * the recorded events and returns, for kernel class `kind` (enum
+ * cqr_kernel_kind), the number of launches, their summed duration in
+ * milliseconds and their summed algorithmic flops and bytes. */
+enum cqr_kernel_kind {
+  CQR_K_GRAM = 0,     /* split-m Gram partials of a panel (SYRK) */
+  CQR_K_PROJ = 1,     /* split-m projection partials Y = Q_j^T Z */
+  CQR_K_UPDATE = 2,   /* trailing update Z -= Q_j Y */
+  CQR_K_TRSM = 3,     /* Q_j = X U^{-1} (explicit inverse, streaming GEMM) */
+  CQR_K_REDUCE = 4,   /* fixed-order sum of split-m partials */
+  CQR_K_CHOL = 5,     /* b x b Cholesky + triangular inverse, one workgroup */
+  CQR_K_SMALL = 6,    /* small R-block products and fills */
+  CQR_K_COPY = 7,     /* A -> Q copy for out-of-place calls */
+  CQR_K_COUNT = 8
+};
+int cqr_profile_enable(int on);
+int cqr_profile_reset(void);
+int cqr_profile_query(int kind, int64_t *launches, double *ms, double *flops,
+                      double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBCQR_CQR_H */

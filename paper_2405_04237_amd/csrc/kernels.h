@@ -1,0 +1,80 @@
+// Internal launch interface of the libcqr device kernels (not part of the
+// C ABI). Every launcher enqueues on `s`, returns hipSuccess or the launch
+// error, and takes the device info word: kernels return early once a
+// Cholesky breakdown has been recorded there.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cqr {
+
+constexpr int kTile = 64;        // output tile edge of the MFMA GEMM kernels
+constexpr int kNnWaves = 4;      // waves per workgroup of the row-streaming GEMM
+constexpr int kMaxPanel = 128;   // largest panel width the LDS Cholesky holds
+
+// Split-m product partials. For chunk c (rows [c*rc, min(m,(c+1)*rc))):
+//   part[c][i*q + j] = sum_rows L[row, i] * Rt[row, j],  i < p, j < q.
+// gram = true: L == Rt, p == q, only 64x64 tiles on or above the diagonal
+// are produced (entries below the diagonal of `part` are left unwritten).
+hipError_t launch_tn(bool gram, int64_t m, int p, int q, const double *L, int64_t ldl,
+                     const double *Rt, int64_t ldr, double *part, int64_t rc, int64_t nch,
+                     const int *info, hipStream_t s);
+
+// Number of 64x64 output tiles one chunk of launch_tn produces.
+int64_t tn_tiles(bool gram, int p, int q);
+
+// Row-streaming product over all m rows, Y row-major p x q (leading dim ldy):
+//   subtract = false: C = L * Y   (C may alias L when q <= 256: each
+//                                   workgroup reads its rows of L fully
+//                                   before it writes them)
+//   subtract = true:  C = C + L * Y, where the caller passes Y = -(the
+//                     projection), so this is the update C -= L * Yproj
+//                     (C must not overlap L)
+// upper_y: Y is upper triangular (only k <= column terms are summed).
+hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const double *L,
+                     int64_t ldl, const double *Y, int64_t ldy, double *C, int64_t ldc,
+                     const int *info, hipStream_t s);
+
+// Leading dimension used for row-major p x q operands written by the
+// library (a multiple of 4 doubles, so rows stay 32-byte aligned).
+__host__ __device__ inline int64_t padded_ld(int64_t q) { return (q + 3) / 4 * 4; }
+
+// Fixed-order (binary-counter pairwise) sum over nch partials of p x q.
+// gram = true: out[i*p + j] = sum for i <= j, 0 below the diagonal.
+// gram = false: out[i*ldo + j] = neg ? -sum : sum; if rblk != nullptr also
+//               rblk[i + j*ldr] = sum (an R block, column-major).
+hipError_t launch_reduce(bool gram, const double *part, int64_t nch, int p, int q, double *out,
+                         int64_t ldo, double *rblk, int64_t ldr, bool neg, const int *info,
+                         hipStream_t s);
+
+// One workgroup: W (row-major w x w, upper triangle read) = U^T U, then
+// U^{-1}. Writes U row-major (ld w) to uout (if non-null), U column-major into
+// the R block rblk (if non-null, strict lower part set to 0), U^{-1}
+// row-major with leading dimension padded_ld(w) to uinv (strict lower part 0). A pivot that is not > 0 sets *info = col0 + i
+// + 1 (first failure wins) and leaves the outputs undefined.
+hipError_t launch_chol_inv(const double *W, int w, double *uout, double *rblk, int64_t ldr,
+                           double *uinv, int *info, int col0, hipStream_t s);
+
+// R[0:s, 0:w] -= Zn * Ua  (R block column-major ldr; Zn = -Z row-major s x w
+//                          with leading dim ldz, as stored by the reduction
+//                          for the update; Ua row-major w x w upper triangular)
+hipError_t launch_r_add_zu(int s_rows, int w, const double *Z, int64_t ldz, const double *Ua,
+                           double *rblk, int64_t ldr, const int *info, hipStream_t s);
+
+// R[0:w, 0:w] = Ub * Ua (both row-major w x w upper triangular); the strict
+// lower part of the block is set to 0.
+hipError_t launch_r_upper_product(int w, const double *Ub, const double *Ua, double *rblk,
+                                  int64_t ldr, const int *info, hipStream_t s);
+
+// R = R2 * R1 for n x n upper triangular column-major matrices (leading
+// dimension n); strict lower part of R set to 0.
+hipError_t launch_trmm_upper(int n, const double *R2, const double *R1, double *R, const int *info,
+                             hipStream_t s);
+
+// p[0:count] = 0
+hipError_t launch_zero(double *p, int64_t count, hipStream_t s);
+
+// *p = v (a kernel, not a memset, so that it is safe inside captured graphs)
+hipError_t launch_set_int(int *p, int v, hipStream_t s);
+
+}  // namespace cqr

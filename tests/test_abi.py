@@ -1,0 +1,96 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+include/cqr.h declares, and its host-only entry points behave (no device
+work is issued by any call here: argument errors return before any HIP call)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2405_04237_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+           if f.endswith(".h")]
+
+
+def declared_functions():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for mt in re.finditer(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(cqr_[a-z_0-9]+)\s*\(", text, re.M):
+            names.add(mt.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libcqr.so missing: run __graft_entry__.build() first")
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert {"cqr_factor", "cqr_factor_ex", "cqr_workspace_bytes", "cqr_get_info"} <= names
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    assert names <= set(_lib.SIGNATURES), names - set(_lib.SIGNATURES)
+
+
+def test_header_constants_match_binding():
+    text = open(os.path.join(ROOT, "include", "cqr.h")).read()
+    assert re.search(r"#define CQR_MAX_PANEL (\d+)", text).group(1) == str(_lib.CQR_MAX_PANEL)
+    for name, val in [("CQR_ERR_ARG", -1), ("CQR_ERR_HIP", -2), ("CQR_ERR_NOMEM", -3),
+                      ("CQR_ERR_WORKSPACE", -4), ("CQR_ERR_UNSUPPORTED", -5)]:
+        assert re.search(rf"{name} = {val}\b", text), name
+        assert getattr(_lib, name) == val
+
+
+def test_workspace_and_panel_queries(lib):
+    assert _lib.workspace_bytes(4096, 64, 16, _lib.SCHED_MOD) > 0
+    assert _lib.workspace_bytes(10, 20, 4, _lib.SCHED_MOD) == 0  # m < n
+    assert _lib.workspace_bytes(4096, 64, -1, _lib.SCHED_MOD) == 0
+    assert _lib.workspace_bytes(4096, 64, 16, 7) == 0
+    # ORIG keeps R1 and R2: more workspace than MOD
+    assert (_lib.workspace_bytes(1 << 20, 256, 64, _lib.SCHED_ORIG)
+            > _lib.workspace_bytes(1 << 20, 256, 64, _lib.SCHED_MOD))
+    for n in (1, 16, 64, 100, 256, 1024):
+        for s in (_lib.SCHED_MOD, _lib.SCHED_ORIG):
+            b = _lib.default_panel(1 << 20, n, s)
+            assert 1 <= b <= min(n, _lib.CQR_MAX_PANEL)
+    assert _lib.status_string(0) == "success"
+    assert "argument" in _lib.status_string(-1)
+
+
+FAKE = C.c_void_p(4096)  # never dereferenced: every call below fails validation first
+
+
+@pytest.mark.parametrize("m,n,b,lda,ptrs,sched,expect", [
+    (10, 20, 4, 10, True, 0, _lib.CQR_ERR_ARG),        # m < n
+    (100, 0, 4, 100, True, 0, _lib.CQR_ERR_ARG),       # n < 1
+    (100, 10, 4, 99, True, 0, _lib.CQR_ERR_ARG),       # lda < m
+    (100, 10, -2, 100, True, 0, _lib.CQR_ERR_ARG),     # b < 0
+    (100, 10, 4, 100, False, 0, _lib.CQR_ERR_ARG),     # null pointers
+    (100, 10, 4, 100, True, 3, _lib.CQR_ERR_ARG),      # bad schedule
+    (1000, 300, 200, 1000, True, 0, _lib.CQR_ERR_UNSUPPORTED),  # b > CQR_MAX_PANEL
+])
+def test_argument_errors(lib, m, n, b, lda, ptrs, sched, expect):
+    p = FAKE if ptrs else None
+    st = _lib.factor_ex(m, n, b, p, lda, p, p, None, sched, None, None, 0)
+    assert st == expect
+    if sched == 0:
+        assert _lib.factor(m, n, b, p, lda, p, p, None) == expect
+
+
+def test_misaligned_pointer_rejected(lib):
+    odd = C.c_void_p(4096 + 4)
+    assert _lib.factor_ex(100, 10, 4, odd, 100, FAKE, FAKE, None, 0, None, None, 0) == _lib.CQR_ERR_ARG
+
+
+def test_small_workspace_rejected(lib):
+    need = _lib.workspace_bytes(100, 10, 4, 0)
+    ws = C.c_void_p(1 << 20)
+    st = _lib.factor_ex(100, 10, 4, FAKE, 100, FAKE, FAKE, None, 0, FAKE, ws, need - 1)
+    assert st == _lib.CQR_ERR_WORKSPACE

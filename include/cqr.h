@@ -99,6 +99,69 @@ size_t cqr_workspace_bytes(int64_t m, int64_t n, int64_t b, int schedule);
 /* Panel width used when b = 0 is passed. */
 int64_t cqr_default_panel(int64_t m, int64_t n, int schedule);
 
+/* Batched factorisation: many independent matrices of uneven shape in one
+ * persistent launch. Each workgroup takes the next matrix from a queue
+ * ordered longest-first (work ~ m n^2) and runs mCQR2GS (Algorithm 9) on it
+ * alone, with its panel reductions over rows finished in the workgroup's
+ * local memory (no cross-workgroup communication).
+ *
+ * cqr_plan_batched (host shapes; allocates and synchronises, so call it
+ * outside graph capture): h_m[i], h_n[i] the shape of matrix i, h_b[i] its
+ * panel width (h_b == NULL or 0 = min(n, 32); clamped to n). Limits of this
+ * form: n <= 128, panel width <= 32; schedule must be CQR_SCHED_MOD
+ * (CQR_ERR_UNSUPPORTED otherwise).
+ *
+ * cqr_factor_batched enqueues a queue reset and one persistent kernel on
+ * `stream` and nothing else: no allocation, no memset, no synchronisation,
+ * so the call can be captured into a HIP graph and replayed. d_A, d_lda,
+ * d_Q, d_R are device arrays (indexed by matrix id) of device pointers and
+ * leading dimensions: A_i and Q_i are m_i x n_i column-major with leading
+ * dimension d_lda[i] >= m_i (Q_i may equal A_i), R_i is n_i x n_i
+ * column-major with leading dimension n_i. d_info[i] receives 0 or the
+ * 1-based breakdown column of matrix i (then Q_i, R_i are undefined). Calls
+ * that use the same plan must not overlap in time (they share its queue). */
+typedef struct cqr_batch_plan cqr_batch_plan;
+int cqr_plan_batched(int64_t batch, const int64_t *h_m, const int64_t *h_n, const int64_t *h_b,
+                     int schedule, cqr_batch_plan **plan);
+int cqr_factor_batched(const cqr_batch_plan *plan, const double *const *d_A,
+                       const int64_t *d_lda, double *const *d_Q, double *const *d_R,
+                       int *d_info, void *stream);
+void cqr_plan_destroy(cqr_batch_plan *plan);
+
+/* Reverse-mode derivative (adjoint) of the thin QR map A -> (Q, R), m >= n,
+ * for full-column-rank A with R's diagonal positive:
+ *     dA = (dQ + Q copyltu(M)) R^{-T},   M = R dR^T - dQ^T Q,
+ * copyltu(M) = tril(M) + tril(M, -1)^T. The paper does not differentiate the
+ * factorisation; this is the published QR adjoint, computed with the same
+ * kernel shapes as the forward factorisation: one split-m pass for the lower
+ * triangle of dQ^T Q (a fixed-order reduction), n x n work for R^{-1} and
+ * copyltu(M) R^{-T}, and one streaming pass dA = [dQ | Q] [R^{-T}; C R^{-T}].
+ *
+ * Q, A, dQ and dA are m x n column-major with leading dimension lda; R and dR
+ * are n x n column-major with leading dimension n. Q == NULL selects the
+ * recompute mode: Q = A R^{-1} is never formed, products with Q are applied
+ * as products with A followed by R^{-1} on the n x n side (A must then be
+ * non-NULL; otherwise A is ignored). dQ and dR may be NULL (zero cotangent);
+ * the strict lower triangle of dR is ignored. dA must not overlap any input.
+ * 1 <= n <= CQR_MAX_PANEL (R^{-1} is formed in one workgroup's LDS).
+ * workspace: >= cqr_backward_workspace_bytes(m, n, batch) bytes of device
+ * memory, 256-byte aligned, or NULL for a buffer the library keeps per device.
+ * Asynchronous on `stream`; bitwise reproducible. Returns CQR_OK or a
+ * negative status (argument errors before any device work). */
+size_t cqr_backward_workspace_bytes(int64_t m, int64_t n, int64_t batch);
+int cqr_backward(int64_t m, int64_t n, const double *Q, const double *A, int64_t lda,
+                 const double *R, const double *dQ, const double *dR, double *dA, void *stream,
+                 void *workspace, size_t workspace_bytes);
+
+/* The adjoint of `batch` equally shaped factorisations in one set of launches
+ * (batch index on the grid). Matrix i of Q, A, dQ and dA starts at base +
+ * i * stride (stride >= lda * n doubles); R and dR at base + i * n * n.
+ * batch <= 65535. */
+int cqr_backward_batched(int64_t batch, int64_t m, int64_t n, const double *Q, const double *A,
+                         int64_t lda, int64_t stride, const double *R, const double *dQ,
+                         const double *dR, double *dA, void *stream, void *workspace,
+                         size_t workspace_bytes);
+
 /* Wait for `stream` and copy the library's internal info word of the current
  * device into *info (host). */
 int cqr_get_info(void *stream, int *info);
@@ -121,7 +184,7 @@ enum cqr_kernel_kind {
   CQR_K_REDUCE = 4,   /* fixed-order sum of split-m partials */
   CQR_K_CHOL = 5,     /* b x b Cholesky + triangular inverse, one workgroup */
   CQR_K_SMALL = 6,    /* small R-block products and fills */
-  CQR_K_COPY = 7,     /* A -> Q copy for out-of-place calls */
+  CQR_K_BATCHED = 7,  /* the persistent batched factorisation (whole launch) */
   CQR_K_COUNT = 8
 };
 int cqr_profile_enable(int on);

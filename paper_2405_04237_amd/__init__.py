@@ -14,8 +14,8 @@ from __future__ import annotations
 from . import _lib
 from ._lib import CqrError, SCHEDULES
 
-__all__ = ["qr", "Breakdown", "CqrError", "empty_colmajor", "as_colmajor", "Workspace",
-           "SCHEDULES"]
+__all__ = ["qr", "qr_batched", "BatchPlan", "BatchedCall", "Breakdown", "CqrError",
+           "empty_colmajor", "as_colmajor", "Workspace", "SCHEDULES"]
 
 
 class Breakdown(ArithmeticError):
@@ -105,3 +105,67 @@ def qr(a, b: int = 0, schedule: str = "mod", check: bool = True, out=None,
         if col:
             raise Breakdown(col)
     return q, r
+
+
+class BatchPlan:
+    """Shapes, longest-first queue order and launch size of a batched call
+    (cqr_plan_batched). Immutable; reusable for any matrices of these shapes."""
+
+    def __init__(self, ms, ns, bs=None, schedule: str = "mod"):
+        self.ms, self.ns = [int(x) for x in ms], [int(x) for x in ns]
+        self.handle = _lib.plan_batched(self.ms, self.ns, bs, SCHEDULES[schedule])
+
+    def __len__(self):
+        return len(self.ms)
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h:
+            _lib.plan_destroy(h)
+
+
+class BatchedCall:
+    """Device argument arrays for repeated cqr_factor_batched launches on the
+    same tensors (e.g. inside a captured HIP graph): launch() enqueues the
+    queue reset and the persistent kernel and nothing else."""
+
+    def __init__(self, mats, bs=None, plan: BatchPlan | None = None, out=None):
+        torch = _torch()
+        for a in mats:
+            _check_input(a)
+            if not (a.stride(0) == 1 and a.stride(1) >= max(1, a.shape[0])):
+                raise ValueError("batched inputs must be column-major")
+        dev = mats[0].device
+        self.a = list(mats)
+        self.plan = plan or BatchPlan([a.shape[0] for a in mats], [a.shape[1] for a in mats], bs)
+        if out is None:
+            self.q = [empty_colmajor(a.shape[0], a.shape[1], dev, ld=a.stride(1)) for a in mats]
+            self.r = [empty_colmajor(a.shape[1], a.shape[1], dev) for a in mats]
+        else:
+            self.q, self.r = out
+        i64 = torch.int64
+        self.d_a = torch.tensor([a.data_ptr() for a in self.a], dtype=i64, device=dev)
+        self.d_q = torch.tensor([q.data_ptr() for q in self.q], dtype=i64, device=dev)
+        self.d_r = torch.tensor([r.data_ptr() for r in self.r], dtype=i64, device=dev)
+        self.d_lda = torch.tensor([a.stride(1) for a in self.a], dtype=i64, device=dev)
+        self.info = torch.zeros(len(self.a), dtype=torch.int32, device=dev)
+
+    def launch(self):
+        torch = _torch()
+        stream = torch.cuda.current_stream(self.d_a.device).cuda_stream
+        st = _lib.factor_batched(self.plan.handle, self.d_a.data_ptr(), self.d_lda.data_ptr(),
+                                 self.d_q.data_ptr(), self.d_r.data_ptr(), self.info.data_ptr(),
+                                 stream)
+        _lib.check(st, "cqr_factor_batched")
+
+
+def qr_batched(mats, bs=None, check: bool = True):
+    """Factor a list of column-major FP64 device matrices of uneven shape in
+    one persistent launch (mCQR2GS each). Returns (Qs, Rs, info)."""
+    call = BatchedCall(mats, bs)
+    call.launch()
+    if check:
+        bad = (call.info != 0).nonzero().flatten().tolist()
+        if bad:
+            raise Breakdown(int(call.info[bad[0]].item()))
+    return call.q, call.r, call.info

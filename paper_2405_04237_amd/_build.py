@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcqr.so")
-SOURCES = ["kernels.hip", "cqr.hip"]
+SOURCES = ["kernels.hip", "batched.hip", "cqr.hip"]
 ARCH = "gfx950"
 
 

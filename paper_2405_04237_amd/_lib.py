@@ -23,7 +23,7 @@ SCHED_MOD = 0
 SCHED_ORIG = 1
 SCHEDULES = {"mod": SCHED_MOD, "orig": SCHED_ORIG}
 
-KERNEL_KINDS = ["gram", "proj", "update", "trsm", "reduce", "chol", "small", "copy"]
+KERNEL_KINDS = ["gram", "proj", "update", "trsm", "reduce", "chol", "small", "batched"]
 
 # Every symbol include/cqr.h declares, with its ctypes signature.
 _I64, _VP, _DP = C.c_int64, C.c_void_p, C.c_void_p
@@ -45,6 +45,13 @@ SIGNATURES = {
     "cqr_profile_reset": (C.c_int, []),
     "cqr_profile_query": (C.c_int, [C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "cqr_plan_batched": (C.c_int, [_I64, _VP, _VP, _VP, C.c_int, C.POINTER(C.c_void_p)]),
+    "cqr_factor_batched": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "cqr_plan_destroy": (None, [_VP]),
+    "cqr_backward_workspace_bytes": (C.c_size_t, [_I64, _I64, _I64]),
+    "cqr_backward": (C.c_int, [_I64, _I64, _DP, _DP, _I64, _DP, _DP, _DP, _DP, _VP, _VP, C.c_size_t]),
+    "cqr_backward_batched": (C.c_int, [_I64, _I64, _I64, _DP, _DP, _I64, _I64, _DP, _DP, _DP, _DP,
+                                       _VP, _VP, C.c_size_t]),
 }
 
 _lib = None
@@ -94,6 +101,42 @@ def factor_ex(m, n, b, a_ptr, lda, q_ptr, r_ptr, stream, schedule, info_ptr, ws_
 
 def factor(m, n, b, a_ptr, lda, q_ptr, r_ptr, stream):
     return int(lib().cqr_factor(m, n, b, a_ptr, lda, q_ptr, r_ptr, stream))
+
+
+def backward_workspace_bytes(m: int, n: int, batch: int = 1) -> int:
+    return int(lib().cqr_backward_workspace_bytes(m, n, batch))
+
+
+def backward(m, n, q_ptr, a_ptr, lda, r_ptr, dq_ptr, dr_ptr, da_ptr, stream, ws_ptr, ws_bytes):
+    return int(lib().cqr_backward(m, n, q_ptr, a_ptr, lda, r_ptr, dq_ptr, dr_ptr, da_ptr, stream,
+                                  ws_ptr, ws_bytes))
+
+
+def backward_batched(batch, m, n, q_ptr, a_ptr, lda, stride, r_ptr, dq_ptr, dr_ptr, da_ptr, stream,
+                     ws_ptr, ws_bytes):
+    return int(lib().cqr_backward_batched(batch, m, n, q_ptr, a_ptr, lda, stride, r_ptr, dq_ptr,
+                                          dr_ptr, da_ptr, stream, ws_ptr, ws_bytes))
+
+
+def plan_batched(ms, ns, bs, schedule: int):
+    import numpy as np
+    m = np.ascontiguousarray(ms, dtype=np.int64)
+    n = np.ascontiguousarray(ns, dtype=np.int64)
+    b = None if bs is None else np.ascontiguousarray(bs, dtype=np.int64)
+    out = C.c_void_p(0)
+    st = lib().cqr_plan_batched(len(m), m.ctypes.data, n.ctypes.data,
+                                None if b is None else b.ctypes.data, schedule, C.byref(out))
+    check(st, "cqr_plan_batched")
+    return out.value
+
+
+def factor_batched(plan, a_ptrs, lda_ptr, q_ptrs, r_ptrs, info_ptr, stream):
+    return int(lib().cqr_factor_batched(plan, a_ptrs, lda_ptr, q_ptrs, r_ptrs, info_ptr, stream))
+
+
+def plan_destroy(plan) -> None:
+    if plan:
+        lib().cqr_plan_destroy(plan)
 
 
 def get_info(stream) -> int:

@@ -11,10 +11,12 @@
 #include <string.h>
 
 #include <algorithm>
+#include <numeric>
 #include <map>
 #include <mutex>
 #include <vector>
 
+#include "batched.h"
 #include "cqr.h"
 #include "kernels.h"
 
@@ -70,6 +72,8 @@ struct DevState {
   void *ws = nullptr;
   size_t ws_bytes = 0;
   int *info = nullptr;
+  void *bwd = nullptr;  // backward workspace
+  size_t bwd_bytes = 0;
 };
 std::mutex g_mu;
 std::map<int, DevState> g_dev;
@@ -163,11 +167,11 @@ hipError_t step_chol(Run &r, int w, double *uout, double *rblk, int64_t ldr, int
   });
 }
 
-// X = X U^{-1} in place (the Q_j := A_j U^{-1} step)
-hipError_t step_trsm(Run &r, double *X, int64_t ldx, int w) {
+// Q = X U^{-1} (the Q_j := A_j U^{-1} step); Q may be X (in place)
+hipError_t step_trsm(Run &r, const double *X, double *Qo, int64_t ld, int w) {
   return timed(r.s, CQR_K_TRSM, double(r.m) * w * w, 16.0 * r.m * w, [&] {
-    return cqr::launch_nn(false, true, r.m, w, w, X, ldx, r.Uinv, cqr::padded_ld(w), X, ldx, r.info,
-                          r.s);
+    return cqr::launch_nn(false, true, r.m, w, w, X, ld, r.Uinv, cqr::padded_ld(w), nullptr, ld, Qo,
+                          ld, r.info, r.s);
   });
 }
 
@@ -186,56 +190,62 @@ hipError_t step_proj(Run &r, const double *Qp, int64_t ld, int p, const double *
   });
 }
 
-// Z -= Qp Y  (r.Y holds -Y)
-hipError_t step_update(Run &r, const double *Qp, int64_t ld, int p, double *Z, int q) {
+// Zo = Zi - Qp Y  (r.Y holds -Y); Zo may be Zi (in place)
+hipError_t step_update(Run &r, const double *Qp, int64_t ld, int p, const double *Zi, double *Zo,
+                       int q) {
   return timed(r.s, CQR_K_UPDATE, 2.0 * r.m * p * q, 8.0 * r.m * (p + 2.0 * q), [&] {
-    return cqr::launch_nn(true, false, r.m, p, q, Qp, ld, r.Y, cqr::padded_ld(q), Z, ld, r.info, r.s);
+    return cqr::launch_nn(true, false, r.m, p, q, Qp, ld, r.Y, cqr::padded_ld(q), Zi, ld, Zo, ld,
+                          r.info, r.s);
   });
 }
 
 // One CQRGS pass (Algorithm 6; Algorithm 8 with the Allreduces replaced by
-// split-m reductions) in place on X, writing its R into Rd (n x n, ld n).
-hipError_t pass_cqrgs(Run &r, double *X, int64_t ld, int64_t b, double *Rd) {
+// split-m reductions), writing Q into X and its R into Rd (n x n, ld n).
+// Columns not yet produced are read from src (A on the first pass, so that
+// A is never copied or written); src may equal X.
+hipError_t pass_cqrgs(Run &r, const double *src, double *X, int64_t ld, int64_t b, double *Rd) {
   const int64_t n = r.n;
   for (int64_t s = 0; s < n; s += b) {
     const int64_t e = std::min(n, s + b);
     const int w = (int)(e - s);
     double *Xj = X + s * ld;
-    CQR_TRY(step_gram(r, Xj, ld, w));                          // W_j := A_j^T A_j
-    CQR_TRY(step_chol(r, w, nullptr, Rd + s + s * n, n, (int)s));  // W_j = U^T U; R_jj := U
-    CQR_TRY(step_trsm(r, Xj, ld, w));                          // Q_j := A_j U^{-1}
+    const double *Aj = (s == 0) ? src : Xj;                          // panel j before its CQR
+    const double *Ar = (s == 0) ? src + e * ld : X + e * ld;         // trailing panels
+    CQR_TRY(step_gram(r, Aj, ld, w));                                // W_j := A_j^T A_j
+    CQR_TRY(step_chol(r, w, nullptr, Rd + s + s * n, n, (int)s));    // W_j = U^T U; R_jj := U
+    CQR_TRY(step_trsm(r, Aj, Xj, ld, w));                            // Q_j := A_j U^{-1}
     if (e < n) {
-      CQR_TRY(step_proj(r, Xj, ld, w, X + e * ld, (int)(n - e), Rd + s + e * n, n));  // Y; R_{j,j+1:k}
-      CQR_TRY(step_update(r, Xj, ld, w, X + e * ld, (int)(n - e)));                   // A_{j+1:k} -= Q_j Y
+      CQR_TRY(step_proj(r, Xj, ld, w, Ar, (int)(n - e), Rd + s + e * n, n));  // Y; R_{j,j+1:k}
+      CQR_TRY(step_update(r, Xj, ld, w, Ar, X + e * ld, (int)(n - e)));       // A_{j+1:k} -= Q_j Y
     }
   }
   return hipSuccess;
 }
 
-hipError_t run_orig(Run &r, double *Q, int64_t ld, int64_t b, double *R) {
+hipError_t run_orig(Run &r, const double *A, double *Q, int64_t ld, int64_t b, double *R) {
   const int64_t n = r.n;
   CQR_TRY(timed(r.s, CQR_K_SMALL, 0, 16.0 * n * n, [&] { return cqr::launch_zero(r.R1, n * n, r.s); }));
   CQR_TRY(timed(r.s, CQR_K_SMALL, 0, 16.0 * n * n, [&] { return cqr::launch_zero(r.R2, n * n, r.s); }));
-  CQR_TRY(pass_cqrgs(r, Q, ld, b, r.R1));  // [Q1, R1] = CQRGS(A)
-  CQR_TRY(pass_cqrgs(r, Q, ld, b, r.R2));  // [Q, R2]  = CQRGS(Q1)
+  CQR_TRY(pass_cqrgs(r, A, Q, ld, b, r.R1));  // [Q1, R1] = CQRGS(A)
+  CQR_TRY(pass_cqrgs(r, Q, Q, ld, b, r.R2));  // [Q, R2]  = CQRGS(Q1)
   const double nf = n;
   return timed(r.s, CQR_K_SMALL, nf * nf * nf / 3.0, 24.0 * nf * nf, [&] {
     return cqr::launch_trmm_upper((int)n, r.R2, r.R1, R, r.info, r.s);  // R = R2 R1
   });
 }
 
-hipError_t run_mod(Run &r, double *Q, int64_t ld, int64_t b, double *R) {
+hipError_t run_mod(Run &r, const double *A, double *Q, int64_t ld, int64_t b, double *R) {
   const int64_t n = r.n;
   CQR_TRY(timed(r.s, CQR_K_SMALL, 0, 8.0 * n * n, [&] { return cqr::launch_zero(R, n * n, r.s); }));
-  // first panel: CholeskyQR2
+  // first panel: CholeskyQR2, reading A_1 and writing Q_1
   {
     const int w = (int)std::min(n, b);
-    CQR_TRY(step_gram(r, Q, ld, w));
+    CQR_TRY(step_gram(r, A, ld, w));
     CQR_TRY(step_chol(r, w, r.Ua, nullptr, 0, 0));
-    CQR_TRY(step_trsm(r, Q, ld, w));
+    CQR_TRY(step_trsm(r, A, Q, ld, w));
     CQR_TRY(step_gram(r, Q, ld, w));
     CQR_TRY(step_chol(r, w, r.Ub, nullptr, 0, 0));
-    CQR_TRY(step_trsm(r, Q, ld, w));
+    CQR_TRY(step_trsm(r, Q, Q, ld, w));
     CQR_TRY(timed(r.s, CQR_K_SMALL, 0, 0, [&] {
       return cqr::launch_r_upper_product(w, r.Ub, r.Ua, R, n, r.info, r.s);  // R_11 = R2 R1
     }));
@@ -244,24 +254,26 @@ hipError_t run_mod(Run &r, double *Q, int64_t ld, int64_t b, double *R) {
     const int64_t ps = s - b, e = std::min(n, s + b);
     const int w = (int)(e - s), pw = (int)b;
     double *Qprev = Q + ps * ld, *Xj = Q + s * ld;
+    // the trailing columns are still A's until the first update writes them to Q
+    const double *Ar = (ps == 0) ? A + s * ld : Xj;
     // Y := Q_{j-1}^T A_{:,j:k}; R_{j-1,j:k} := Y; A_{:,j:k} -= Q_{j-1} Y
-    CQR_TRY(step_proj(r, Qprev, ld, pw, Xj, (int)(n - s), R + ps + s * n, n));
-    CQR_TRY(step_update(r, Qprev, ld, pw, Xj, (int)(n - s)));
+    CQR_TRY(step_proj(r, Qprev, ld, pw, Ar, (int)(n - s), R + ps + s * n, n));
+    CQR_TRY(step_update(r, Qprev, ld, pw, Ar, Xj, (int)(n - s)));
     // CQR(A_j): A_j = Qt Ua
     CQR_TRY(step_gram(r, Xj, ld, w));
     CQR_TRY(step_chol(r, w, r.Ua, nullptr, 0, (int)s));
-    CQR_TRY(step_trsm(r, Xj, ld, w));
+    CQR_TRY(step_trsm(r, Xj, Xj, ld, w));
     // re-orthogonalise: Z := Q_{1:j-1}^T Qt; Qt -= Q_{1:j-1} Z; R_{1:j-1,j} += Z Ua
     // (r.Y holds -Z, so the R update subtracts (-Z) Ua)
     CQR_TRY(step_proj(r, Q, ld, (int)s, Xj, w, nullptr, 0));
-    CQR_TRY(step_update(r, Q, ld, (int)s, Xj, w));
+    CQR_TRY(step_update(r, Q, ld, (int)s, Xj, Xj, w));
     CQR_TRY(timed(r.s, CQR_K_SMALL, 2.0 * s * w * w / 2, 0, [&] {
       return cqr::launch_r_add_zu((int)s, w, r.Y, cqr::padded_ld(w), r.Ua, R + s * n, n, r.info, r.s);
     }));
     // CQR again: Qt = Q_j Ub; R_jj = Ub Ua
     CQR_TRY(step_gram(r, Xj, ld, w));
     CQR_TRY(step_chol(r, w, r.Ub, nullptr, 0, (int)s));
-    CQR_TRY(step_trsm(r, Xj, ld, w));
+    CQR_TRY(step_trsm(r, Xj, Xj, ld, w));
     CQR_TRY(timed(r.s, CQR_K_SMALL, 0, 0, [&] {
       return cqr::launch_r_upper_product(w, r.Ub, r.Ua, R + s + s * n, n, r.info, r.s);
     }));
@@ -279,6 +291,51 @@ int check_args(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda, co
   if (misaligned(A, 8) || misaligned(Q, 8) || misaligned(R, 8)) return CQR_ERR_ARG;
   if (schedule != CQR_SCHED_MOD && schedule != CQR_SCHED_ORIG) return CQR_ERR_ARG;
   if (effective_panel(m, n, b, schedule) > kMaxPanel) return CQR_ERR_UNSUPPORTED;
+  return CQR_OK;
+}
+
+// ---------------------------------------------------------------- backward
+struct BwdLayout {
+  int64_t info, part, t, rinv, c, g, y, total;
+  int64_t nch, rc, ldy;
+};
+
+BwdLayout make_bwd_layout(int64_t m, int64_t n, int64_t batch) {
+  BwdLayout L{};
+  const int64_t tiles = cqr::tn_tiles(true, (int)n, (int)n);
+  int64_t want = (kTargetWaves + tiles * batch - 1) / (tiles * batch);
+  want = std::max(want, (m + kMaxChunkRows - 1) / kMaxChunkRows);
+  want = std::min({want, (m + 15) / 16, int64_t(1024)});
+  want = std::max<int64_t>(want, 1);
+  L.rc = round_up((m + want - 1) / want, 16);
+  L.nch = (m + L.rc - 1) / L.rc;
+  L.ldy = cqr::padded_ld(n);
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t o = off;
+    off = round_up(off + bytes, kAlign);
+    return o;
+  };
+  L.info = take(kAlign);
+  L.part = take(8 * batch * L.nch * n * n);
+  L.t = take(8 * batch * n * n);
+  L.rinv = take(8 * batch * n * n);
+  L.c = take(8 * batch * n * n);
+  L.g = take(8 * batch * n * n);
+  L.y = take(8 * batch * 2 * n * L.ldy);
+  L.total = off;
+  return L;
+}
+
+int check_bwd(int64_t batch, int64_t m, int64_t n, const double *Q, const double *A, int64_t lda,
+              int64_t stride, const double *R, const double *dQ, const double *dR, const double *dA) {
+  if (batch < 1 || batch > 65535 || n < 1 || m < n || lda < std::max<int64_t>(1, m)) return CQR_ERR_ARG;
+  if (batch > 1 && stride < lda * n) return CQR_ERR_ARG;
+  if (!R || !dA || (!Q && !A)) return CQR_ERR_ARG;
+  const void *ptrs[] = {Q, A, R, dQ, dR, dA};
+  for (const void *p : ptrs)
+    if (p && misaligned(p, 8)) return CQR_ERR_ARG;
+  if (n > kMaxPanel) return CQR_ERR_UNSUPPORTED;
   return CQR_OK;
 }
 
@@ -361,14 +418,8 @@ int cqr_factor_ex(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
 
   if (timed(s, CQR_K_SMALL, 0, 0, [&] { return cqr::launch_set_int(info, 0, s); }) != hipSuccess)
     return CQR_ERR_HIP;
-  if (Q != A) {
-    const hipError_t e = timed(s, CQR_K_COPY, 0, 16.0 * m * n, [&] {
-      return hipMemcpy2DAsync(Q, lda * 8, A, lda * 8, m * 8, n, hipMemcpyDeviceToDevice, s);
-    });
-    if (e != hipSuccess) return CQR_ERR_HIP;
-  }
-  const hipError_t e = (schedule == CQR_SCHED_ORIG) ? run_orig(r, Q, lda, be, R)
-                                                    : run_mod(r, Q, lda, be, R);
+  const hipError_t e = (schedule == CQR_SCHED_ORIG) ? run_orig(r, A, Q, lda, be, R)
+                                                    : run_mod(r, A, Q, lda, be, R);
   return e == hipSuccess ? CQR_OK : CQR_ERR_HIP;
 }
 
@@ -449,6 +500,202 @@ int cqr_profile_query(int kind, int64_t *launches, double *ms, double *flops, do
   if (flops) *flops = a.flops;
   if (bytes) *bytes = a.bytes;
   return CQR_OK;
+}
+
+size_t cqr_backward_workspace_bytes(int64_t m, int64_t n, int64_t batch) {
+  if (batch < 1 || n < 1 || m < n) return 0;
+  return (size_t)make_bwd_layout(m, n, batch).total;
+}
+
+int cqr_backward_batched(int64_t batch, int64_t m, int64_t n, const double *Q, const double *A,
+                         int64_t lda, int64_t stride, const double *R, const double *dQ,
+                         const double *dR, double *dA, void *stream, void *workspace,
+                         size_t workspace_bytes) {
+  const int st = check_bwd(batch, m, n, Q, A, lda, stride, R, dQ, dR, dA);
+  if (st != CQR_OK) return st;
+  if (batch == 1) stride = lda * n;
+  const BwdLayout lay = make_bwd_layout(m, n, batch);
+  hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  if (ws) {
+    if (workspace_bytes < (size_t)lay.total) return CQR_ERR_WORKSPACE;
+    if (misaligned(ws, kAlign)) return CQR_ERR_ARG;
+  } else {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CQR_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState &d = g_dev[dev];
+    if (d.bwd_bytes < (size_t)lay.total) {
+      if (d.bwd) {
+        if (hipDeviceSynchronize() != hipSuccess) return CQR_ERR_HIP;
+        if (hipFree(d.bwd) != hipSuccess) return CQR_ERR_HIP;
+        d.bwd = nullptr;
+        d.bwd_bytes = 0;
+      }
+      if (hipMalloc(&d.bwd, (size_t)lay.total) != hipSuccess) return CQR_ERR_NOMEM;
+      d.bwd_bytes = (size_t)lay.total;
+    }
+    ws = (char *)d.bwd;
+  }
+  int *info = (int *)(ws + lay.info);
+  double *part = (double *)(ws + lay.part), *T = (double *)(ws + lay.t);
+  double *Rinv = (double *)(ws + lay.rinv), *C = (double *)(ws + lay.c), *G = (double *)(ws + lay.g);
+  double *Y = (double *)(ws + lay.y);
+  const int ni = (int)n, b = (int)batch;
+  const int64_t nn = n * n, sy = 2 * n * lay.ldy;
+  const bool recompute = (Q == nullptr);
+  const double *S = recompute ? A : Q;
+  const double mf = (double)m, nf = (double)n, bf = (double)batch;
+  auto fail = [](hipError_t e) { return e == hipSuccess ? CQR_OK : CQR_ERR_HIP; };
+
+  if (!dQ && !dR)
+    return fail(timed(s, CQR_K_SMALL, 0, 8.0 * bf * mf * nf,
+                      [&] { return cqr::launch_zero2d(dA, m, n, lda, stride, b, s); }));
+  hipError_t e = cqr::launch_set_int(info, 0, s);
+  if (e != hipSuccess) return CQR_ERR_HIP;
+  // pass 1: T = S^T dQ (upper 64x64 tiles), split over m, fixed-order reduce
+  if (dQ) {
+    e = timed(s, CQR_K_PROJ, bf * mf * nf * nf, 16.0 * bf * mf * nf, [&] {
+      return cqr::launch_tn(true, m, ni, ni, S, lda, dQ, lda, part, lay.rc, lay.nch, info, s, b,
+                            stride, stride, lay.nch * nn);
+    });
+    if (e != hipSuccess) return CQR_ERR_HIP;
+    e = timed(s, CQR_K_REDUCE, bf * lay.nch * nn, 8.0 * bf * (lay.nch + 1) * nn, [&] {
+      return cqr::launch_reduce(true, part, lay.nch, ni, ni, T, n, nullptr, 0, false, info, s, b,
+                                lay.nch * nn, nn, 0);
+    });
+    if (e != hipSuccess) return CQR_ERR_HIP;
+  }
+  // n x n part: R^{-1}, C = copyltu(M), the stacked right operand
+  e = timed(s, CQR_K_CHOL, bf * nf * nf * nf / 3.0, 16.0 * bf * nn,
+            [&] { return cqr::launch_tri_inv(R, ni, nn, Rinv, nn, b, s); });
+  if (e != hipSuccess) return CQR_ERR_HIP;
+  e = timed(s, CQR_K_SMALL, bf * 2.0 * nf * nf * nf, 8.0 * bf * 6 * nn, [&] {
+    return cqr::launch_adj_small(ni, T, nn, R, dR, nn, Rinv, nn, dQ ? 1 : 0, recompute ? 1 : 0, C, G,
+                                 nn, Y, lay.ldy, sy, dQ ? 1 : 0, b, s);
+  });
+  if (e != hipSuccess) return CQR_ERR_HIP;
+  // pass 2: dA = [dQ | S] [R^{-T}; G]   (or S G when dQ is absent)
+  if (dQ) {
+    e = timed(s, CQR_K_UPDATE, bf * 4.0 * mf * nf * nf, 24.0 * bf * mf * nf, [&] {
+      return cqr::launch_nn(false, false, m, 2 * ni, ni, dQ, lda, Y, lay.ldy, nullptr, 0, dA, lda,
+                            info, s, S, lda, ni, b, stride, stride, sy, 0, stride);
+    });
+  } else {
+    e = timed(s, CQR_K_UPDATE, bf * 2.0 * mf * nf * nf, 16.0 * bf * mf * nf, [&] {
+      return cqr::launch_nn(false, false, m, ni, ni, S, lda, Y, lay.ldy, nullptr, 0, dA, lda, info,
+                            s, nullptr, 0, 0, b, stride, 0, sy, 0, stride);
+    });
+  }
+  return fail(e);
+}
+
+int cqr_backward(int64_t m, int64_t n, const double *Q, const double *A, int64_t lda,
+                 const double *R, const double *dQ, const double *dR, double *dA, void *stream,
+                 void *workspace, size_t workspace_bytes) {
+  return cqr_backward_batched(1, m, n, Q, A, lda, lda * n, R, dQ, dR, dA, stream, workspace,
+                              workspace_bytes);
+}
+
+// ---------------------------------------------------------------- batched
+}  // extern "C"
+
+struct cqr_batch_plan {
+  int64_t count = 0;
+  int device = 0;
+  int grid = 0;
+  void *mem = nullptr;  // order | m | n | b | queue
+  int *order = nullptr;
+  int64_t *m = nullptr;
+  int *n = nullptr;
+  int *b = nullptr;
+  int *queue = nullptr;
+  double flops = 0, bytes = 0;
+};
+
+extern "C" {
+
+int cqr_plan_batched(int64_t batch, const int64_t *h_m, const int64_t *h_n, const int64_t *h_b,
+                     int schedule, cqr_batch_plan **plan) {
+  if (!plan) return CQR_ERR_ARG;
+  *plan = nullptr;
+  if (batch < 1 || batch > (int64_t(1) << 30) || !h_m || !h_n) return CQR_ERR_ARG;
+  if (schedule != CQR_SCHED_MOD && schedule != CQR_SCHED_ORIG) return CQR_ERR_ARG;
+  if (schedule != CQR_SCHED_MOD) return CQR_ERR_UNSUPPORTED;
+  std::vector<int64_t> m(h_m, h_m + batch);
+  std::vector<int> n(batch), b(batch);
+  double flops = 0, bytes = 0;
+  for (int64_t i = 0; i < batch; ++i) {
+    if (h_n[i] < 1 || m[i] < h_n[i] || m[i] > (int64_t(1) << 40)) return CQR_ERR_ARG;
+    const int64_t bi = h_b ? h_b[i] : 0;
+    if (bi < 0) return CQR_ERR_ARG;
+    const int64_t be = std::min<int64_t>(bi == 0 ? cqr::kBatchMaxPanel : bi, h_n[i]);
+    if (h_n[i] > cqr::kBatchMaxN || be > cqr::kBatchMaxPanel) return CQR_ERR_UNSUPPORTED;
+    n[i] = (int)h_n[i];
+    b[i] = (int)be;
+    const double mf = (double)m[i], nf = n[i];
+    flops += 2.0 * mf * nf * nf - 2.0 * nf * nf * nf / 3.0;  // Householder-equivalent
+    bytes += 24.0 * mf * nf + 24.0 * mf * nf * nf / be;
+  }
+  // longest processing time first: work ~ m n^2, ties by index
+  std::vector<int> order(batch);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (double)m[x] * n[x] * n[x] > (double)m[y] * n[y] * n[y];
+  });
+  cqr_batch_plan *pl = new cqr_batch_plan();
+  pl->count = batch;
+  if (hipGetDevice(&pl->device) != hipSuccess) {
+    delete pl;
+    return CQR_ERR_HIP;
+  }
+  const size_t so = round_up(4 * batch, kAlign), sm = round_up(8 * batch, kAlign);
+  const size_t sn = round_up(4 * batch, kAlign), sb = round_up(4 * batch, kAlign);
+  if (hipMalloc(&pl->mem, so + sm + sn + sb + kAlign) != hipSuccess) {
+    delete pl;
+    return CQR_ERR_NOMEM;
+  }
+  char *base = (char *)pl->mem;
+  pl->order = (int *)base;
+  pl->m = (int64_t *)(base + so);
+  pl->n = (int *)(base + so + sm);
+  pl->b = (int *)(base + so + sm + sn);
+  pl->queue = (int *)(base + so + sm + sn + sb);
+  bool ok = hipMemcpy(pl->order, order.data(), 4 * batch, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(pl->m, m.data(), 8 * batch, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(pl->n, n.data(), 4 * batch, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(pl->b, b.data(), 4 * batch, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemset(pl->queue, 0, sizeof(int)) == hipSuccess;
+  int cus = 0;
+  ok = ok && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) ==
+                 hipSuccess;
+  if (!ok) {
+    (void)hipFree(pl->mem);
+    delete pl;
+    return CQR_ERR_HIP;
+  }
+  pl->grid = (int)std::min<int64_t>(batch, (int64_t)cus * cqr::batched_blocks_per_cu());
+  pl->flops = flops;
+  pl->bytes = bytes;
+  *plan = pl;
+  return CQR_OK;
+}
+
+int cqr_factor_batched(const cqr_batch_plan *plan, const double *const *d_A, const int64_t *d_lda,
+                       double *const *d_Q, double *const *d_R, int *d_info, void *stream) {
+  if (!plan || !d_A || !d_lda || !d_Q || !d_R || !d_info) return CQR_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const hipError_t e = timed(s, CQR_K_BATCHED, plan->flops, plan->bytes, [&] {
+    return cqr::launch_batched_mod(plan->grid, plan->order, plan->m, plan->n, plan->b,
+                                   (int)plan->count, d_A, d_lda, d_Q, d_R, d_info, plan->queue, s);
+  });
+  return e == hipSuccess ? CQR_OK : CQR_ERR_HIP;
+}
+
+void cqr_plan_destroy(cqr_batch_plan *plan) {
+  if (!plan) return;
+  if (plan->mem) (void)hipFree(plan->mem);
+  delete plan;
 }
 
 }  // extern "C"

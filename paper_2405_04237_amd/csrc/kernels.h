@@ -14,38 +14,50 @@ constexpr int kMaxPanel = 128;   // largest panel width the LDS Cholesky holds
 
 // Split-m product partials. For chunk c (rows [c*rc, min(m,(c+1)*rc))):
 //   part[c][i*q + j] = sum_rows L[row, i] * Rt[row, j],  i < p, j < q.
-// gram = true: L == Rt, p == q, only 64x64 tiles on or above the diagonal
-// are produced (entries below the diagonal of `part` are left unwritten).
+// gram = true: p == q and only 64x64 tiles on or above the diagonal are
+// produced (entries below the diagonal of `part` are left unwritten); L and
+// Rt may differ (a Gram matrix passes the same matrix twice).
+// batch > 1: `batch` independent problems of the same shape, operand i at
+// base + i * stride (strides in doubles).
 hipError_t launch_tn(bool gram, int64_t m, int p, int q, const double *L, int64_t ldl,
                      const double *Rt, int64_t ldr, double *part, int64_t rc, int64_t nch,
-                     const int *info, hipStream_t s);
+                     const int *info, hipStream_t s, int batch = 1, int64_t sL = 0,
+                     int64_t sRt = 0, int64_t sPart = 0);
 
 // Number of 64x64 output tiles one chunk of launch_tn produces.
 int64_t tn_tiles(bool gram, int p, int q);
 
 // Row-streaming product over all m rows, Y row-major p x q (leading dim ldy):
-//   subtract = false: C = L * Y   (C may alias L when q <= 256: each
-//                                   workgroup reads its rows of L fully
+//   subtract = false: C = L * Y   (Cin unused; C may alias L when q <= 256:
+//                                   each workgroup reads its rows of L fully
 //                                   before it writes them)
-//   subtract = true:  C = C + L * Y, where the caller passes Y = -(the
-//                     projection), so this is the update C -= L * Yproj
-//                     (C must not overlap L)
+//   subtract = true:  C = Cin + L * Y, where the caller passes Y = -(the
+//                     projection), so this is the update C = Cin - L * Yproj.
+//                     Cin may equal C (in place); neither may overlap L.
 // upper_y: Y is upper triangular (only k <= column terms are summed).
+// L2/ldl2/psplit: optional second left operand; rows k >= psplit of Y
+// multiply columns k - psplit of L2, i.e. the left operand is
+// [L(:, 0:psplit) | L2]. L2 = nullptr means L alone.
 hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const double *L,
-                     int64_t ldl, const double *Y, int64_t ldy, double *C, int64_t ldc,
-                     const int *info, hipStream_t s);
+                     int64_t ldl, const double *Y, int64_t ldy, const double *Cin, int64_t ldci,
+                     double *C, int64_t ldc, const int *info, hipStream_t s,
+                     const double *L2 = nullptr, int64_t ldl2 = 0, int psplit = 0, int batch = 1,
+                     int64_t sL = 0, int64_t sL2 = 0, int64_t sY = 0, int64_t sCin = 0,
+                     int64_t sC = 0);
 
 // Leading dimension used for row-major p x q operands written by the
 // library (a multiple of 4 doubles, so rows stay 32-byte aligned).
 __host__ __device__ inline int64_t padded_ld(int64_t q) { return (q + 3) / 4 * 4; }
 
-// Fixed-order (binary-counter pairwise) sum over nch partials of p x q.
+// Fixed-order (pairwise) sum over nch partials of p x q. The partial buffer
+// is used as scratch (overwritten) when nch is large.
 // gram = true: out[i*p + j] = sum for i <= j, 0 below the diagonal.
 // gram = false: out[i*ldo + j] = neg ? -sum : sum; if rblk != nullptr also
 //               rblk[i + j*ldr] = sum (an R block, column-major).
-hipError_t launch_reduce(bool gram, const double *part, int64_t nch, int p, int q, double *out,
+hipError_t launch_reduce(bool gram, double *part, int64_t nch, int p, int q, double *out,
                          int64_t ldo, double *rblk, int64_t ldr, bool neg, const int *info,
-                         hipStream_t s);
+                         hipStream_t s, int batch = 1, int64_t sPart = 0, int64_t sOut = 0,
+                         int64_t sR = 0);
 
 // One workgroup: W (row-major w x w, upper triangle read) = U^T U, then
 // U^{-1}. Writes U row-major (ld w) to uout (if non-null), U column-major into
@@ -54,6 +66,25 @@ hipError_t launch_reduce(bool gram, const double *part, int64_t nch, int p, int 
 // + 1 (first failure wins) and leaves the outputs undefined.
 hipError_t launch_chol_inv(const double *W, int w, double *uout, double *rblk, int64_t ldr,
                            double *uinv, int *info, int col0, hipStream_t s);
+
+// Rinv = R^{-1} for `batch` upper triangular n x n matrices (R column-major
+// ld n at R + i*sR; Rinv row-major ld n at Rinv + i*sRi); n <= kMaxPanel.
+hipError_t launch_tri_inv(const double *R, int n, int64_t sR, double *Rinv, int64_t sRi, int batch,
+                          hipStream_t s);
+
+// The n x n part of the QR adjoint, per matrix i of the batch:
+//   C = copyltu(R dR^T - P) with P = dQ^T Q taken from T = S^T dQ (upper
+//   triangle of a row-major n x n; S = Q, or A when recompute != 0, in which
+//   case Q = A R^{-1} is applied through Rinv); has_p = 0 drops P, dR =
+//   nullptr drops R dR^T;
+//   G = C R^{-T};
+//   Y (row-major, ld ldy) = [R^{-T}; G] (with_rt) or [G], where G becomes
+//   R^{-1} G under recompute.
+// C and G are n x n row-major scratch at C + i*sCG, G + i*sCG.
+hipError_t launch_adj_small(int n, const double *T, int64_t sT, const double *R, const double *dR,
+                            int64_t sRn, const double *Rinv, int64_t sRi, int has_p, int recompute,
+                            double *C, double *G, int64_t sCG, double *Y, int64_t ldy, int64_t sY,
+                            int with_rt, int batch, hipStream_t s);
 
 // R[0:s, 0:w] -= Zn * Ua  (R block column-major ldr; Zn = -Z row-major s x w
 //                          with leading dim ldz, as stored by the reduction
@@ -73,6 +104,11 @@ hipError_t launch_trmm_upper(int n, const double *R2, const double *R1, double *
 
 // p[0:count] = 0
 hipError_t launch_zero(double *p, int64_t count, hipStream_t s);
+
+// zero `batch` column-major rows x cols blocks (leading dim ld, block i at
+// p + i*sb)
+hipError_t launch_zero2d(double *p, int64_t rows, int64_t cols, int64_t ld, int64_t sb, int batch,
+                         hipStream_t s);
 
 // *p = v (a kernel, not a memset, so that it is safe inside captured graphs)
 hipError_t launch_set_int(int *p, int v, hipStream_t s);

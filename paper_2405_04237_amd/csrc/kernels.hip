@@ -27,42 +27,31 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "device_common.h"
 #include "kernels.h"
 
 namespace cqr {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2). Renumber so that each XCD receives a contiguous range of logical
-// block ids: neighbouring logical blocks (which share input rows) then share
-// an L2.
-__device__ __forceinline__ int64_t xcd_logical(int64_t bid, int64_t nb) {
-  constexpr int64_t kXcd = 8;
-  const int64_t full = nb / kXcd * kXcd;
-  if (bid >= full) return bid;
-  return (bid % kXcd) * (full / kXcd) + bid / kXcd;
-}
-
 // ----------------------------------------------------------------------------
 // k_tn: split-m partial products. One wave per (row chunk, 64x64 tile).
+// UPPER: only tiles on or above the diagonal (p == q), e.g. a Gram matrix.
 // ----------------------------------------------------------------------------
-template <bool GRAM, bool VEC>
+template <bool UPPER, bool VEC>
 __global__ __launch_bounds__(64) void k_tn(int64_t m, int p, int q, const double *__restrict__ L,
                                            int64_t ldl, const double *__restrict__ Rt, int64_t ldr,
                                            double *__restrict__ part, int64_t rc, int tp, int tq,
+                                           int64_t sL, int64_t sRt, int64_t sPart,
                                            const int *__restrict__ info) {
   if (*info) return;
+  L += blockIdx.y * sL;  // batch: one matrix per grid row
+  Rt += blockIdx.y * sRt;
+  part += blockIdx.y * sPart;
   const int64_t lid = xcd_logical(blockIdx.x, gridDim.x);
-  const int T = GRAM ? tp * (tp + 1) / 2 : tp * tq;
+  const int T = UPPER ? tp * (tp + 1) / 2 : tp * tq;
   const int64_t c = lid / T;
   int t = (int)(lid % T);
   int ti, tj;
-  if (GRAM) {
+  if (UPPER) {
     ti = 0;
     int len = tp;
     while (t >= len) {
@@ -132,25 +121,33 @@ __global__ __launch_bounds__(64) void k_tn(int64_t m, int p, int q, const double
         for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x4(da[x][s], db[y][s], acc[x][y]);
   };
 
-  double a0[4][4], b0[4][4], a1[4][4], b1[4][4];
+  // Three register sets in a ring: while one step's 64 MFMAs run, the loads
+  // of the next two steps are in flight (about 8K cycles of cover at the
+  // FP64 MFMA rate). The scheduling barriers keep the compiler from sinking
+  // the loads next to their uses. Prefetch offsets are clamped to the last
+  // full step, so every load stays inside the chunk.
+  double a0[4][4], b0[4][4], a1[4][4], b1[4][4], a2[4][4], b2[4][4];
   if (nsteps > 0) {
-    // Ping-pong over two register sets, the next step's loads issued before
-    // this step's MFMAs (the scheduling barriers keep the compiler from
-    // sinking the loads next to their uses). The prefetch offset is clamped
-    // to the last full step, so every load stays inside the chunk.
+    auto at = [&](int64_t st) -> int64_t { return 16 * (st < nsteps ? st : nsteps - 1); };
     load(a0, b0, 0);
+    load(a1, b1, at(1));
     int64_t it = 0;
-    for (; it + 2 <= nsteps; it += 2) {
-      load(a1, b1, 16 * (it + 1));
+    for (; it + 3 <= nsteps; it += 3) {
+      load(a2, b2, at(it + 2));
       __builtin_amdgcn_sched_barrier(0);
       compute(a0, b0);
       __builtin_amdgcn_sched_barrier(0);
-      load(a0, b0, 16 * ((it + 2 < nsteps) ? it + 2 : nsteps - 1));
+      load(a0, b0, at(it + 3));
       __builtin_amdgcn_sched_barrier(0);
       compute(a1, b1);
       __builtin_amdgcn_sched_barrier(0);
+      load(a1, b1, at(it + 4));
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a2, b2);
+      __builtin_amdgcn_sched_barrier(0);
     }
     if (it < nsteps) compute(a0, b0);
+    if (it + 1 < nsteps) compute(a1, b1);
   }
   const int64_t rt = rb + 16 * nsteps;
   if (rt < re) {  // ragged tail: rows rt + 4g + s < re only
@@ -185,23 +182,22 @@ int64_t tn_tiles(bool gram, int p, int q) {
 
 hipError_t launch_tn(bool gram, int64_t m, int p, int q, const double *L, int64_t ldl,
                      const double *Rt, int64_t ldr, double *part, int64_t rc, int64_t nch,
-                     const int *info, hipStream_t s) {
+                     const int *info, hipStream_t s, int batch, int64_t sL, int64_t sRt,
+                     int64_t sPart) {
   const int tp = (p + kTile - 1) / kTile, tq = (q + kTile - 1) / kTile;
   const int64_t nb = tn_tiles(gram, p, q) * nch;
   const bool vec = (ldl % 2 == 0) && (ldr % 2 == 0) && ((uintptr_t)L % 16 == 0) &&
-                   ((uintptr_t)Rt % 16 == 0) && (rc % 16 == 0);
-  dim3 grid((unsigned)nb), block(64);
+                   ((uintptr_t)Rt % 16 == 0) && (rc % 16 == 0) && (sL % 2 == 0) && (sRt % 2 == 0);
+  dim3 grid((unsigned)nb, (unsigned)batch), block(64);
+#define CQR_TN(U, V)                                                                             \
+  hipLaunchKernelGGL((k_tn<U, V>), grid, block, 0, s, m, p, q, L, ldl, Rt, ldr, part, rc, tp, tq, \
+                     sL, sRt, sPart, info)
   if (gram) {
-    if (vec)
-      hipLaunchKernelGGL((k_tn<true, true>), grid, block, 0, s, m, p, q, L, ldl, Rt, ldr, part, rc, tp, tq, info);
-    else
-      hipLaunchKernelGGL((k_tn<true, false>), grid, block, 0, s, m, p, q, L, ldl, Rt, ldr, part, rc, tp, tq, info);
+    if (vec) CQR_TN(true, true); else CQR_TN(true, false);
   } else {
-    if (vec)
-      hipLaunchKernelGGL((k_tn<false, true>), grid, block, 0, s, m, p, q, L, ldl, Rt, ldr, part, rc, tp, tq, info);
-    else
-      hipLaunchKernelGGL((k_tn<false, false>), grid, block, 0, s, m, p, q, L, ldl, Rt, ldr, part, rc, tp, tq, info);
+    if (vec) CQR_TN(false, true); else CQR_TN(false, false);
   }
+#undef CQR_TN
   return hipGetLastError();
 }
 
@@ -220,10 +216,20 @@ hipError_t launch_tn(bool gram, int64_t m, int p, int q, const double *L, int64_
 // ----------------------------------------------------------------------------
 template <bool SUB, bool TRI, bool VEC>
 __global__ __launch_bounds__(256) void k_nn(int64_t m, int p, int q, const double *L, int64_t ldl,
-                                            const double *__restrict__ Y, int64_t ldy, double *C,
-                                            int64_t ldc, int wr, int ncg,
-                                            const int *__restrict__ info) {
+                                            const double *L2, int64_t ldl2, int psplit,
+                                            const double *__restrict__ Y, int64_t ldy,
+                                            const double *Cin, int64_t ldci, double *C, int64_t ldc,
+                                            int wr, int ncg, int64_t sL, int64_t sL2, int64_t sY,
+                                            int64_t sCin, int64_t sC, const int *__restrict__ info) {
   if (*info) return;
+  {  // batch: one matrix per grid row
+    const int64_t bi = blockIdx.y;
+    L += bi * sL;
+    L2 += bi * sL2;
+    Y += bi * sY;
+    Cin += bi * sCin;
+    C += bi * sC;
+  }
   const int64_t lid = xcd_logical(blockIdx.x, gridDim.x);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
   const int wc = 4 / wr;
@@ -246,7 +252,7 @@ __global__ __launch_bounds__(256) void k_nn(int64_t m, int p, int q, const doubl
         for (int x = 0; x < 4; ++x) {
           const int col = c0 + 4 * g + 16 * e + x;
           if (col < q) {
-            const double *pc = C + (int64_t)col * ldc + rl;
+            const double *pc = Cin + (int64_t)col * ldci + rl;
             if (VEC && rl + 4 <= m) {
               const double2 v0 = reinterpret_cast<const double2 *>(pc)[0];
               const double2 v1 = reinterpret_cast<const double2 *>(pc)[1];
@@ -271,13 +277,14 @@ __global__ __launch_bounds__(256) void k_nn(int64_t m, int p, int q, const doubl
     // multiple of 4 at the right edge) takes the masked loop below.
     const bool fast = (r0 + kTile <= m) && ((q % 4) == 0 || c0 + kTile <= q);
     const double *lb = L + rl;
+    const double *lb2 = L2 + rl;  // k >= psplit reads L2[:, k - psplit]
     const double *yb = Y + (yc < q ? yc : 0);
     auto load = [&](double (&da)[4][4], double (&db)[4][4], int kk) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int k = kk + 4 * s + g;
         const double *py = yb + (int64_t)k * ldy;
-        const double *pl = lb + (int64_t)k * ldl;
+        const double *pl = (k < psplit) ? lb + (int64_t)k * ldl : lb2 + (int64_t)(k - psplit) * ldl2;
         if (VEC) {
           const double2 y0 = reinterpret_cast<const double2 *>(py)[0];
           const double2 y1 = reinterpret_cast<const double2 *>(py)[1];
@@ -308,22 +315,30 @@ __global__ __launch_bounds__(256) void k_nn(int64_t m, int p, int q, const doubl
 #pragma unroll
           for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x4(da[s][x], db[s][y], acc[x][y]);
     };
-    double a0[4][4], b0[4][4], a1[4][4], b1[4][4];
+    // three-deep register ring, as in k_tn
+    double a0[4][4], b0[4][4], a1[4][4], b1[4][4], a2[4][4], b2[4][4];
     const int nit = fast ? kend / 16 : 0;  // full 16-wide k iterations
     if (nit > 0) {
+      auto at = [&](int st) -> int { return 16 * (st < nit ? st : nit - 1); };
       load(a0, b0, 0);
+      load(a1, b1, at(1));
       int it = 0;
-      for (; it + 2 <= nit; it += 2) {
-        load(a1, b1, 16 * (it + 1));
+      for (; it + 3 <= nit; it += 3) {
+        load(a2, b2, at(it + 2));
         __builtin_amdgcn_sched_barrier(0);
         compute(a0, b0);
         __builtin_amdgcn_sched_barrier(0);
-        load(a0, b0, 16 * ((it + 2 < nit) ? it + 2 : nit - 1));
+        load(a0, b0, at(it + 3));
         __builtin_amdgcn_sched_barrier(0);
         compute(a1, b1);
         __builtin_amdgcn_sched_barrier(0);
+        load(a1, b1, at(it + 4));
+        __builtin_amdgcn_sched_barrier(0);
+        compute(a2, b2);
+        __builtin_amdgcn_sched_barrier(0);
       }
       if (it < nit) compute(a0, b0);
+      if (it + 1 < nit) compute(a1, b1);
     }
     // k tail (and the whole k range off the fast path): masked element loads
     for (int kk = 16 * nit; kk < kend; kk += 16) {
@@ -334,7 +349,8 @@ __global__ __launch_bounds__(256) void k_nn(int64_t m, int p, int q, const doubl
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           a0[s][u] = (kok && yc + u < q) ? Y[(int64_t)k * ldy + yc + u] : 0.0;
-          b0[s][u] = (kok && rl + u < m) ? L[(int64_t)k * ldl + rl + u] : 0.0;
+          const double *lk = (k < psplit) ? L + (int64_t)k * ldl : L2 + (int64_t)(k - psplit) * ldl2;
+          b0[s][u] = (kok && rl + u < m) ? lk[rl + u] : 0.0;
         }
       }
       compute(a0, b0);
@@ -362,20 +378,36 @@ __global__ __launch_bounds__(256) void k_nn(int64_t m, int p, int q, const doubl
 }
 
 hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const double *L,
-                     int64_t ldl, const double *Y, int64_t ldy, double *C, int64_t ldc,
-                     const int *info, hipStream_t s) {
+                     int64_t ldl, const double *Y, int64_t ldy, const double *Cin, int64_t ldci,
+                     double *C, int64_t ldc, const int *info, hipStream_t s, const double *L2,
+                     int64_t ldl2, int psplit, int batch, int64_t sL, int64_t sL2, int64_t sY,
+                     int64_t sCin, int64_t sC) {
+  if (!L2) {
+    L2 = L;
+    ldl2 = ldl;
+    sL2 = sL;
+    psplit = p;
+  }
+  if (!Cin) {
+    Cin = C;
+    ldci = ldc;
+    sCin = sC;
+  }
   const int slabs = (q + kTile - 1) / kTile;
   const int wc = slabs >= 4 ? 4 : (slabs >= 2 ? 2 : 1);
   const int wr = 4 / wc;
   const int ncg = (slabs + wc - 1) / wc;
   if (!subtract && ncg != 1) return hipErrorInvalidValue;  // in-place needs one column group
   const int64_t rts = (m + (int64_t)kTile * wr - 1) / ((int64_t)kTile * wr);
-  const bool vec = (ldl % 2 == 0) && (ldc % 2 == 0) && (ldy % 2 == 0) && ((uintptr_t)L % 16 == 0) &&
-                   ((uintptr_t)C % 16 == 0) && ((uintptr_t)Y % 16 == 0);
-  dim3 grid((unsigned)(rts * ncg)), block(256);
+  const bool vec = (ldl % 2 == 0) && (ldl2 % 2 == 0) && (ldc % 2 == 0) && (ldci % 2 == 0) &&
+                   (ldy % 2 == 0) && ((uintptr_t)L % 16 == 0) && ((uintptr_t)L2 % 16 == 0) &&
+                   ((uintptr_t)C % 16 == 0) && ((uintptr_t)Cin % 16 == 0) &&
+                   ((uintptr_t)Y % 16 == 0) && (sL % 2 == 0) && (sL2 % 2 == 0) && (sY % 2 == 0) &&
+                   (sCin % 2 == 0) && (sC % 2 == 0);
+  dim3 grid((unsigned)(rts * ncg), (unsigned)batch), block(256);
 #define CQR_NN(S, T, V)                                                                          \
-  hipLaunchKernelGGL((k_nn<S, T, V>), grid, block, 0, s, m, p, q, L, ldl, Y, ldy, C, ldc, wr, ncg, \
-                     info)
+  hipLaunchKernelGGL((k_nn<S, T, V>), grid, block, 0, s, m, p, q, L, ldl, L2, ldl2, psplit, Y, ldy, \
+                     Cin, ldci, C, ldc, wr, ncg, sL, sL2, sY, sCin, sC, info)
   if (subtract) {
     if (vec) CQR_NN(true, false, true); else CQR_NN(true, false, false);
   } else if (upper_y) {
@@ -387,17 +419,81 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
   return hipGetLastError();
 }
 // ----------------------------------------------------------------------------
-// k_reduce: fixed-order sum of split-m partials (replaces the Allreduce of
-// Algorithms 2 and 8). Element e of every partial is summed by one thread in
-// a binary-counter pairwise order over the chunk index, so the result does
-// not depend on which wave finished first.
+// Split-m reduction: fixed-order sum of the per-chunk partials (replaces the
+// Allreduce of Algorithms 2 and 8). Element e of the chunk partials is summed
+// by one thread: groups of 8 consecutive chunks are loaded together (8
+// independent loads in flight) and added in a fixed pairwise tree; the group
+// sums go through a binary-counter pairwise accumulator held in registers.
+// Large chunk counts are cut into slices of kSlice chunks summed by separate
+// blocks, whose results are summed the same way by a second pass. The order
+// depends only on (chunk count, element), never on which wave finished first.
 // ----------------------------------------------------------------------------
+constexpr int kSlice = 64;
+
+__device__ __forceinline__ double pairwise_sum(const double *__restrict__ x, int64_t count,
+                                               int64_t stride) {
+  double lvl[24];
+  unsigned occ = 0;
+  for (int64_t c0 = 0; c0 < count; c0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (c0 + u < count) ? x[(c0 + u) * stride] : 0.0;
+    double g = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    bool placed = false;
+#pragma unroll
+    for (int l = 0; l < 24; ++l) {
+      if (!placed) {
+        if (occ & (1u << l)) {
+          g = lvl[l] + g;
+          occ &= ~(1u << l);
+        } else {
+          lvl[l] = g;
+          occ |= 1u << l;
+          placed = true;
+        }
+      }
+    }
+  }
+  double sum = 0.0;
+  bool first = true;
+#pragma unroll
+  for (int l = 0; l < 24; ++l)
+    if (occ & (1u << l)) {
+      sum = first ? lvl[l] : lvl[l] + sum;
+      first = false;
+    }
+  return sum;
+}
+
+// pass 1: block (x, s) sums chunks [s kSlice, (s+1) kSlice) of its elements
+// into the slice's first chunk slot
 template <bool GRAM>
-__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ part, int64_t nch, int p,
-                                                int q, double *__restrict__ out, int64_t ldo,
+__global__ __launch_bounds__(256) void k_reduce_slices(double *part, int64_t nch, int p, int q,
+                                                       int64_t sPart, const int *__restrict__ info) {
+  if (*info) return;
+  part += blockIdx.z * sPart;
+  const int64_t pq = (int64_t)p * q;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= pq) return;
+  if (GRAM && (int)(e / q) > (int)(e % q)) return;
+  const int64_t c0 = (int64_t)blockIdx.y * kSlice;
+  const int64_t cnt = (nch - c0 < kSlice) ? nch - c0 : kSlice;
+  const double v = pairwise_sum(part + c0 * pq + e, cnt, pq);
+  part[c0 * pq + e] = v;
+}
+
+// pass 2 (or the only pass): sum `count` values spaced `stride` apart
+template <bool GRAM>
+__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ part, int64_t count,
+                                                int64_t stride, int p, int q,
+                                                double *__restrict__ out, int64_t ldo,
                                                 double *__restrict__ rblk, int64_t ldr, bool neg,
+                                                int64_t sPart, int64_t sOut, int64_t sR,
                                                 const int *__restrict__ info) {
   if (*info) return;
+  part += blockIdx.z * sPart;
+  out += blockIdx.z * sOut;
+  if (rblk) rblk += blockIdx.z * sR;
   const int64_t pq = (int64_t)p * q;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= pq) return;
@@ -406,15 +502,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ part,
     out[(int64_t)i * p + j] = 0.0;
     return;
   }
-  double stk[40];
-  int top = 0;
-  for (int64_t c = 0; c < nch; ++c) {
-    double v = part[c * pq + e];
-    for (uint64_t k = (uint64_t)c + 1; (k & 1) == 0; k >>= 1) v = stk[--top] + v;
-    stk[top++] = v;
-  }
-  double sum = stk[top - 1];
-  for (int t = top - 2; t >= 0; --t) sum = stk[t] + sum;
+  const double sum = pairwise_sum(part + e, count, stride);
   if (GRAM) {
     out[(int64_t)i * p + j] = sum;
   } else {
@@ -423,17 +511,31 @@ __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ part,
   }
 }
 
-hipError_t launch_reduce(bool gram, const double *part, int64_t nch, int p, int q, double *out,
+hipError_t launch_reduce(bool gram, double *part, int64_t nch, int p, int q, double *out,
                          int64_t ldo, double *rblk, int64_t ldr, bool neg, const int *info,
-                         hipStream_t s) {
+                         hipStream_t s, int batch, int64_t sPart, int64_t sOut, int64_t sR) {
   const int64_t pq = (int64_t)p * q;
-  dim3 grid((unsigned)((pq + 255) / 256)), block(256);
+  const unsigned bx = (unsigned)((pq + 255) / 256);
+  int64_t count = nch, stride = pq;
+  if (nch > kSlice) {
+    const unsigned ns = (unsigned)((nch + kSlice - 1) / kSlice);
+    dim3 g(bx, ns, (unsigned)batch);
+    if (gram)
+      hipLaunchKernelGGL((k_reduce_slices<true>), g, dim3(256), 0, s, part, nch, p, q, sPart, info);
+    else
+      hipLaunchKernelGGL((k_reduce_slices<false>), g, dim3(256), 0, s, part, nch, p, q, sPart, info);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    count = ns;
+    stride = pq * kSlice;
+  }
+  dim3 g(bx, 1, (unsigned)batch);
   if (gram)
-    hipLaunchKernelGGL((k_reduce<true>), grid, block, 0, s, part, nch, p, q, out, ldo, rblk, ldr, neg,
-                       info);
+    hipLaunchKernelGGL((k_reduce<true>), g, dim3(256), 0, s, part, count, stride, p, q, out, ldo, rblk,
+                       ldr, neg, sPart, sOut, sR, info);
   else
-    hipLaunchKernelGGL((k_reduce<false>), grid, block, 0, s, part, nch, p, q, out, ldo, rblk, ldr, neg,
-                       info);
+    hipLaunchKernelGGL((k_reduce<false>), g, dim3(256), 0, s, part, count, stride, p, q, out, ldo,
+                       rblk, ldr, neg, sPart, sOut, sR, info);
   return hipGetLastError();
 }
 
@@ -451,70 +553,33 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double *__restr
                                                            double *__restrict__ rblk, int64_t ldr,
                                                            double *__restrict__ uinv, int *info,
                                                            int col0) {
-  extern __shared__ double S[];  // w*w matrix, then w diagonal entries of X
-  __shared__ int fail;
+  // S: w*w matrix (upper: W, then U; strict lower: X = U^{-1}, transposed);
+  // D: the diagonal of U, then of X
+  extern __shared__ double S[];
   if (*info) return;
   double *D = S + w * w;
   const int tid = threadIdx.x, nt = blockDim.x;
-  if (tid == 0) fail = 0;
   for (int e = tid; e < w * w; e += nt) {
     const int i = e / w, j = e % w;
     S[e] = (i <= j) ? W[e] : 0.0;
   }
   __syncthreads();
-  for (int k = 0; k < w; ++k) {
-    if (tid == 0) {
-      const double d = S[k * w + k];
-      if (d > 0.0)
-        S[k * w + k] = sqrt(d);
-      else
-        fail = k + 1;  // also taken for NaN
-    }
-    __syncthreads();
-    if (fail) break;
-    const double piv = S[k * w + k];
-    for (int j = k + 1 + tid; j < w; j += nt) S[k * w + j] = S[k * w + j] / piv;
-    __syncthreads();
-    const int rem = w - k - 1;
-    for (int e = tid; e < rem * rem; e += nt) {
-      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
-      if (j >= i) S[i * w + j] = S[i * w + j] - S[k * w + i] * S[k * w + j];
-    }
-    __syncthreads();
-  }
+  const int fail = lds_cholesky(S, D, w);
   if (fail) {
     if (tid == 0) atomicCAS(info, 0, col0 + fail);
     return;
   }
   for (int e = tid; e < w * w; e += nt) {
     const int i = e / w, j = e % w;
-    const double u = (i <= j) ? S[e] : 0.0;
+    const double u = (i < j) ? S[e] : (i == j ? D[i] : 0.0);
     if (uout) uout[e] = u;
     if (rblk) rblk[i + (int64_t)j * ldr] = u;
   }
-  // inverse: X = U^{-1}; X[i][c] (i < c) lives at S[c*w + i], X[k][k] at D[k]
-  for (int k = tid; k < w; k += nt) D[k] = 1.0;
+  __syncthreads();  // D is reused for the diagonal of X below
+  // U's diagonal moves to S[k*w + k] for the inverse
+  for (int k = tid; k < w; k += nt) S[k * w + k] = D[k];
   __syncthreads();
-  for (int k = w - 1; k >= 0; --k) {
-    const double ukk = S[k * w + k];
-    for (int c = k + tid; c < w; c += nt) {
-      if (c == k)
-        D[k] = D[k] / ukk;
-      else
-        S[c * w + k] = S[c * w + k] / ukk;
-    }
-    __syncthreads();
-    const int cols = w - k;
-    for (int e = tid; e < k * cols; e += nt) {
-      const int i = e % k, c = k + e / k;
-      const double xkc = (c == k) ? D[k] : S[c * w + k];
-      if (c == k)
-        S[k * w + i] = S[k * w + i] - S[i * w + k] * xkc;
-      else
-        S[c * w + i] = S[c * w + i] - S[i * w + k] * xkc;
-    }
-    __syncthreads();
-  }
+  lds_upper_inverse(S, D, w);
   const int ldu = (int)padded_ld(w);
   for (int e = tid; e < w * ldu; e += nt) {
     const int i = e / ldu, c = e % ldu;
@@ -536,6 +601,142 @@ hipError_t launch_chol_inv(const double *W, int w, double *uout, double *rblk, i
   }
   hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kCholThreads), lds, s, W, w, uout, rblk, ldr, uinv,
                      info, col0);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Small n x n kernels of the QR adjoint dA = (dQ + Q copyltu(M)) R^{-T},
+// M = R dR^T - dQ^T Q. One matrix per blockIdx.y (batched), n <= kMaxPanel.
+// ----------------------------------------------------------------------------
+// Rinv = R^{-1}, R column-major (ld n), Rinv row-major (ld n); one workgroup
+// per matrix.
+__global__ __launch_bounds__(kCholThreads) void k_tri_inv(const double *__restrict__ R, int n,
+                                                          int64_t sR, double *__restrict__ Rinv,
+                                                          int64_t sRi) {
+  extern __shared__ double S[];
+  double *D = S + n * n;
+  R += blockIdx.x * sR;
+  Rinv += blockIdx.x * sRi;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < n * n; e += nt) {
+    const int i = e / n, j = e % n;
+    S[e] = (i <= j) ? R[i + (int64_t)j * n] : 0.0;
+  }
+  __syncthreads();
+  lds_upper_inverse(S, D, n);
+  for (int e = tid; e < n * n; e += nt) {
+    const int i = e / n, c = e % n;
+    Rinv[e] = (c < i) ? 0.0 : (c == i ? D[i] : S[c * n + i]);
+  }
+}
+
+hipError_t launch_tri_inv(const double *R, int n, int64_t sR, double *Rinv, int64_t sRi, int batch,
+                          hipStream_t s) {
+  if (n < 1 || n > kMaxPanel) return hipErrorInvalidValue;
+  const size_t lds = ((size_t)n * n + n) * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {
+    const size_t most = ((size_t)kMaxPanel * kMaxPanel + kMaxPanel) * sizeof(double);
+    const hipError_t e = hipFuncSetAttribute((const void *)k_tri_inv,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)most);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_tri_inv, dim3((unsigned)batch), dim3(kCholThreads), lds, s, R, n, sR, Rinv,
+                     sRi);
+  return hipGetLastError();
+}
+
+// C = copyltu(M), M = R dR^T - P on and below the diagonal (row-major C).
+// P = dQ^T Q from T = S^T dQ (upper triangle valid, row-major, ld n):
+//   Q given:    P[i][j] = T[j][i]
+//   recompute:  S = A and Q = A R^{-1}, so P[i][j] = sum_{k<=j} T[k][i] Rinv[k][j]
+// dR == nullptr or has_p == 0 drop the corresponding term.
+__global__ __launch_bounds__(256) void k_adj_c(int n, const double *__restrict__ T, int64_t sT,
+                                               const double *__restrict__ R,
+                                               const double *__restrict__ dR, int64_t sRn,
+                                               const double *__restrict__ Rinv, int64_t sRi,
+                                               int has_p, int recompute, double *__restrict__ C,
+                                               int64_t sC) {
+  const int64_t bi = blockIdx.y;
+  T += bi * sT;
+  R += bi * sRn;
+  if (dR) dR += bi * sRn;
+  Rinv += bi * sRi;
+  C += bi * sC;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * n) return;
+  const int i = e / n, j = e % n;
+  if (i < j) return;
+  double rdr = 0.0;
+  if (dR)
+    for (int k = i; k < n; ++k) rdr += R[i + (int64_t)k * n] * dR[j + (int64_t)k * n];
+  double pv = 0.0;
+  if (has_p) {
+    if (recompute)
+      for (int k = 0; k <= j; ++k) pv += T[k * n + i] * Rinv[k * n + j];
+    else
+      pv = T[j * n + i];
+  }
+  const double mv = rdr - pv;
+  C[i * n + j] = mv;
+  C[j * n + i] = mv;
+}
+
+// G = C R^{-T}: G[k][c] = sum_{l >= c} C[k][l] Rinv[c][l]   (row-major)
+__global__ __launch_bounds__(256) void k_adj_g(int n, const double *__restrict__ C, int64_t sC,
+                                               const double *__restrict__ Rinv, int64_t sRi,
+                                               double *__restrict__ G, int64_t sG) {
+  const int64_t bi = blockIdx.y;
+  C += bi * sC;
+  Rinv += bi * sRi;
+  G += bi * sG;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * n) return;
+  const int k = e / n, c = e % n;
+  double acc = 0.0;
+  for (int l = c; l < n; ++l) acc += C[k * n + l] * Rinv[c * n + l];
+  G[e] = acc;
+}
+
+// The right operand of the streaming pass, row-major with leading dim ldy:
+//   rows [0, n) (only if with_rt): R^{-T};  rows [off, off + n): G, or
+//   R^{-1} G when Q is recomputed from A (the pass then multiplies A).
+__global__ __launch_bounds__(256) void k_adj_y(int n, const double *__restrict__ G, int64_t sG,
+                                               const double *__restrict__ Rinv, int64_t sRi,
+                                               int with_rt, int recompute, double *__restrict__ Y,
+                                               int64_t ldy, int64_t sY) {
+  const int64_t bi = blockIdx.y;
+  G += bi * sG;
+  Rinv += bi * sRi;
+  Y += bi * sY;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * n) return;
+  const int k = e / n, c = e % n;
+  const int off = with_rt ? n : 0;
+  if (with_rt) Y[(int64_t)k * ldy + c] = (c <= k) ? Rinv[c * n + k] : 0.0;
+  double g;
+  if (recompute) {
+    g = 0.0;
+    for (int j = k; j < n; ++j) g += Rinv[k * n + j] * G[j * n + c];
+  } else {
+    g = G[e];
+  }
+  Y[(int64_t)(off + k) * ldy + c] = g;
+}
+
+hipError_t launch_adj_small(int n, const double *T, int64_t sT, const double *R, const double *dR,
+                            int64_t sRn, const double *Rinv, int64_t sRi, int has_p, int recompute,
+                            double *C, double *G, int64_t sCG, double *Y, int64_t ldy, int64_t sY,
+                            int with_rt, int batch, hipStream_t s) {
+  dim3 g((unsigned)((n * n + 255) / 256), (unsigned)batch), blk(256);
+  hipLaunchKernelGGL(k_adj_c, g, blk, 0, s, n, T, sT, R, dR, sRn, Rinv, sRi, has_p, recompute, C, sCG);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_g, g, blk, 0, s, n, C, sCG, Rinv, sRi, G, sCG);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_y, g, blk, 0, s, n, G, sCG, Rinv, sRi, with_rt, recompute, Y, ldy, sY);
   return hipGetLastError();
 }
 
@@ -606,6 +807,26 @@ hipError_t launch_trmm_upper(int n, const double *R2, const double *R1, double *
 __global__ __launch_bounds__(256) void k_zero(double *p, int64_t count) {
   const int64_t stride = (int64_t)gridDim.x * 256;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += stride) p[e] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_zero2d(double *p, int64_t rows, int64_t cols, int64_t ld,
+                                                int64_t sb) {
+  double *base = p + blockIdx.y * sb;
+  const int64_t count = rows * cols;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += stride)
+    base[(e / rows) * ld + e % rows] = 0.0;
+}
+
+hipError_t launch_zero2d(double *p, int64_t rows, int64_t cols, int64_t ld, int64_t sb, int batch,
+                         hipStream_t s) {
+  const int64_t count = rows * cols;
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_zero2d, dim3((unsigned)blocks, (unsigned)batch), dim3(256), 0, s, p, rows, cols,
+                     ld, sb);
+  return hipGetLastError();
 }
 
 __global__ void k_set_int(int *p, int v) { *p = v; }

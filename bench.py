@@ -44,7 +44,7 @@ def log(*a):
 
 def kernel_sha() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.h", "cqr.hip"):
+    for f in ("kernels.hip", "kernels.h", "device_common.h", "batched.hip", "batched.h", "cqr.hip"):
         h.update(open(os.path.join(ROOT, "paper_2405_04237_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -60,6 +60,112 @@ def traffic_for(kind: str, workload: str):
         return None
     k = d.get("per_launch", {}).get(kind)
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+
+
+def bench_batched(steps: int, warmup: int):
+    """The batched workload (512 matrices of uneven shape) in one persistent
+    launch, captured in a HIP graph and replayed; inputs generated on the host
+    (the recipe of matgen.batch_problems) and uploaded before timing."""
+    import numpy as np
+    import torch
+    import matgen
+    import paper_2405_04237_amd as cqr
+    from paper_2405_04237_amd import measure
+    probs = matgen.batch_problems()
+    log(f"batched: generating {len(probs)} matrices on the host")
+    mats = []
+    for p in probs:
+        a = matgen.test_matrix(p.m, p.n, p.kappa, p.seed)
+        mats.append(torch.from_numpy(np.ascontiguousarray(a.T)).to("cuda").t())
+    call = cqr.BatchedCall(mats, bs=[p.b for p in probs])
+    call.launch()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            call.launch()
+    torch.cuda.current_stream().wait_stream(st)
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    hh = sum(2.0 * p.m * p.n ** 2 - 2.0 * p.n ** 3 / 3 for p in probs)
+    nbytes = sum(24.0 * p.m * p.n + 24.0 * p.m * p.n ** 2 / p.b for p in probs)
+    worst = max(measure.orthogonality(q) for q in call.q)
+    info = int((call.info != 0).sum().item())
+    return {"workload": f"{len(probs)} matrices, m in [2048, 65536], n in {{16,32,64,128}}, "
+                        "b = min(ceil(n/2), 32), kappa log-uniform in [1e2, 1e14]",
+            "ms": round(ms, 3), "value": round(hh / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+            "graph": True, "max_orthogonality": worst, "breakdowns": info,
+            "roofline": {"bound": "hbm", "achieved": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                         "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                         "frac": round(nbytes / (ms * 1e-3) / PEAK_HBM, 4),
+                         "bytes_model": "sum 24 m n + 24 m n^2 / b"}}
+
+
+def bench_backward(steps: int, warmup: int):
+    """The adjoint at 262144 x 128 (kappa 1e6) and batched 64 x 32768 x 64
+    (kappa 1e4), dQ and dR ~ N(0, 1), Q and R from this library's forward."""
+    import torch
+    import matgen
+    import paper_2405_04237_amd as cqr
+    from paper_2405_04237_amd import autograd as cag
+    from paper_2405_04237_amd.costs import backward_bytes, backward_flops
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    out = {}
+    m, n = 262144, 128
+    a = torch.from_numpy(matgen.test_matrix(m, n, 1e6, seed=55).T.copy()).to("cuda").t()
+    dq, dr = matgen.cotangents(m, n, seed=55)
+    dq = torch.from_numpy(dq.T.copy()).to("cuda").t()
+    dr = torch.from_numpy(dr.T.copy()).to("cuda").t()
+    q, r = cqr.qr(a)
+    for mode, kw in (("stored_q", {"q": q}), ("recompute_q", {"a": a})):
+        ms = timed(lambda: cag.qr_backward(r, dq=dq, dr=dr, **kw))
+        fl, by = backward_flops(m, n), backward_bytes(m, n)
+        out[mode] = {"workload": f"{m} x {n}, kappa=1e6", "ms": round(ms, 4),
+                     "tflops": round(fl / (ms * 1e-3) / 1e12, 3),
+                     "gbs": round(by / (ms * 1e-3) / 1e9, 1),
+                     "roofline": {"bound": "mfma", "frac": round(fl / (ms * 1e-3) / PEAK_FP64, 4)}}
+    bsz, m2, n2 = 64, 32768, 64
+    log("backward: generating the batched inputs")
+    qs, rs = [], []
+    for i in range(bsz):
+        ai = matgen.test_matrix(m2, n2, 1e4, seed=500 + i) if i < 8 else None
+        ai = ai if ai is not None else matgen.test_matrix(m2, n2, 1e4, seed=500 + i % 8)
+        qi, ri = cqr.qr(torch.from_numpy(ai.T.copy()).to("cuda").t())
+        qs.append(qi), rs.append(ri)
+    Q = torch.stack(qs)
+    R = torch.stack(rs)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    dQ = torch.randn((bsz, n2, m2), dtype=torch.float64, device="cuda", generator=g).transpose(1, 2)
+    dR = torch.triu(torch.randn((bsz, n2, n2), dtype=torch.float64, device="cuda", generator=g))
+    ms = timed(lambda: cag.qr_backward_batched(R, dq=dQ, dr=dR, q=Q))
+    by = bsz * backward_bytes(m2, n2)
+    out["batched"] = {"workload": f"{bsz} x ({m2} x {n2}), kappa=1e4", "ms": round(ms, 4),
+                      "gbs": round(by / (ms * 1e-3) / 1e9, 1),
+                      "roofline": {"bound": "hbm", "frac": round(by / (ms * 1e-3) / PEAK_HBM, 4)}}
+    return out
 
 
 def cpu_baseline(w: dict, b: int, schedule: str, rows: int):
@@ -97,8 +203,12 @@ def main():
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--schedule", default="mod", choices=["mod", "orig"])
     ap.add_argument("--b", type=int, default=0, help="panel width (0 = autotune)")
-    ap.add_argument("--cpu-rows", type=int, default=1 << 17)
+    ap.add_argument("--cpu-rows", type=int, default=1 << 18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched and adjoint measurements")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="finish with one 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -200,6 +310,19 @@ def main():
         "info": info, "wall_s": round(wall, 3), "roofline": roof, "kernels": kern,
         "tune": table,
     }
+    del q, r, ws, a
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        out["batched"] = bench_batched(max(args.steps, 3), 1)
+        log(f"batched: {out['batched']['ms']} ms")
+        out["backward"] = bench_backward(max(args.steps, 5), 2)
+        log("backward: " + json.dumps(out["backward"]))
+    if args.calibration_copy:
+        x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        y = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        x.copy_(y)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = 2 * 8 * (1 << 27)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, b, args.schedule, min(args.cpu_rows, m))
     print(json.dumps(out), flush=True)

@@ -107,7 +107,7 @@ int64_t cqr_default_panel(int64_t m, int64_t n, int schedule);
  *
  * cqr_plan_batched (host shapes; allocates and synchronises, so call it
  * outside graph capture): h_m[i], h_n[i] the shape of matrix i, h_b[i] its
- * panel width (h_b == NULL or 0 = min(n, 32); clamped to n). Limits of this
+ * panel width (h_b == NULL or 0 = min(ceil(n / 2), 32); clamped to n). Limits of this
  * form: n <= 128, panel width <= 32; schedule must be CQR_SCHED_MOD
  * (CQR_ERR_UNSUPPORTED otherwise).
  *

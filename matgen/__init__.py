@@ -169,12 +169,12 @@ def batch_problems(count: int = 512, seed: int = 4, m_lo: int = 2048,
                    m_hi: int = 65536, n_set=(16, 32, 64, 128), b_cap: int = 32,
                    logk_lo: float = 2.0, logk_hi: float = 14.0) -> list[Problem]:
     """Shapes of the batched workload: m ~ U{m_lo..m_hi}, n ~ U(n_set),
-    b = min(n, b_cap), log10 kappa ~ U[logk_lo, logk_hi], one seed each."""
+    b = min(ceil(n / 2), b_cap), log10 kappa ~ U[logk_lo, logk_hi], one seed each."""
     rng = np.random.default_rng(seed_sequence(seed, count))
     ms = rng.integers(m_lo, m_hi + 1, size=count)
     ns = rng.choice(np.asarray(n_set), size=count)
     ks = 10.0 ** rng.uniform(logk_lo, logk_hi, size=count)
-    return [Problem(int(ms[i]), int(ns[i]), int(min(ns[i], b_cap)), float(ks[i]),
+    return [Problem(int(ms[i]), int(ns[i]), int(min((ns[i] + 1) // 2, b_cap)), float(ks[i]),
                     1000 * seed + i) for i in range(count)]
 
 

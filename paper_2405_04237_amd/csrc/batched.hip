@@ -23,7 +23,11 @@ namespace cqr {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kFlushRows = 4096;  // rows accumulated in registers before an LDS flush
+// Row sums are accumulated on three levels so that no running sum takes more
+// than a few hundred sequential additions: MFMA accumulators over kInnerRows
+// rows, a second register set over kFlushRows rows, then the LDS result.
+constexpr int kInnerRows = 512;
+constexpr int kFlushRows = 4096;
 
 // LDS layout (doubles)
 constexpr int kYSize = kBatchMaxPanel * kBatchMaxN + 64;  // projections (+ read slack)
@@ -45,10 +49,13 @@ __device__ inline Lds lds_layout(double *base) {
   return L;
 }
 
-// Writes by one wave become visible to the other waves of the workgroup.
+// Global-memory writes made by one wave before the barrier are visible to
+// every wave of the workgroup after it: release fence, barrier, then an
+// acquire fence that drops stale vector-L1 lines (agent scope on both sides).
 __device__ inline void wg_sync() {
   __threadfence();
   __syncthreads();
+  __threadfence();
 }
 
 // out (LDS, row-major, ld ldo) = L^T Rt over rows [0, m); L is m x p, Rt m x q
@@ -99,39 +106,54 @@ __device__ __forceinline__ void wg_tn(int64_t m, int p, int q, const double *L, 
       pa[t] = L + (int64_t)(ca < p ? ca : 0) * ldl + 4 * g;
       pb[t] = Rt + (int64_t)(cb < q ? cb : 0) * ldr + 4 * g;
     }
-    d4 acc[4];
-    auto flush = [&]() {
+    d4 acc[4], acc2[4];
+    auto fold = [&]() {  // acc2 += acc; acc = 0
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc2[t][e] += acc[t][e];
+        acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+      }
+    };
+    auto flush = [&]() {  // out += acc2; acc2 = 0
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         if (t < nb) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int I = 16 * bi[t] + g + 4 * e, J = 16 * bj[t] + cl;
-            if (I < p && J < q) out[I * ldo + J] += acc[t][e];
+            if (I < p && J < q) out[I * ldo + J] += acc2[t][e];
           }
         }
-        acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+        acc2[t] = d4{0.0, 0.0, 0.0, 0.0};
       }
     };
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < 4; ++t) {
+      acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+      acc2[t] = d4{0.0, 0.0, 0.0, 0.0};
+    }
     const int64_t full = m / 16 * 16;
     double a[4][4], b[4][4];
     for (int64_t r0 = 0; r0 < full; r0 += kFlushRows) {
       const int64_t r1 = (r0 + kFlushRows < full) ? r0 + kFlushRows : full;
-      for (int64_t r = r0; r < r1; r += 16) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            a[t][s] = pa[t][r + s];
-            b[t][s] = pb[t][r + s];
-          }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
+      for (int64_t ri = r0; ri < r1; ri += kInnerRows) {
+        const int64_t r2 = (ri + kInnerRows < r1) ? ri + kInnerRows : r1;
+        for (int64_t r = ri; r < r2; r += 16) {
 #pragma unroll
           for (int t = 0; t < 4; ++t)
-            if (t < nb) acc[t] = mfma16x16x4(a[t][s], b[t][s], acc[t]);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              a[t][s] = pa[t][r + s];
+              b[t][s] = pb[t][r + s];
+            }
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (t < nb) acc[t] = mfma16x16x4(a[t][s], b[t][s], acc[t]);
+        }
+        fold();
       }
       flush();
     }
@@ -149,6 +171,7 @@ __device__ __forceinline__ void wg_tn(int64_t m, int p, int q, const double *L, 
 #pragma unroll
         for (int t = 0; t < 4; ++t)
           if (t < nb) acc[t] = mfma16x16x4(a[t][s], b[t][s], acc[t]);
+      fold();
       flush();
     }
   }

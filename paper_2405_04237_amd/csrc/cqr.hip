@@ -629,7 +629,10 @@ int cqr_plan_batched(int64_t batch, const int64_t *h_m, const int64_t *h_n, cons
     if (h_n[i] < 1 || m[i] < h_n[i] || m[i] > (int64_t(1) << 40)) return CQR_ERR_ARG;
     const int64_t bi = h_b ? h_b[i] : 0;
     if (bi < 0) return CQR_ERR_ARG;
-    const int64_t be = std::min<int64_t>(bi == 0 ? cqr::kBatchMaxPanel : bi, h_n[i]);
+    // default: two or more panels, at most kBatchMaxPanel wide (a single panel
+    // is plain CholeskyQR2, which breaks down for kappa beyond about 1e8)
+    const int64_t bdef = std::min<int64_t>((h_n[i] + 1) / 2, cqr::kBatchMaxPanel);
+    const int64_t be = std::min<int64_t>(bi == 0 ? bdef : bi, h_n[i]);
     if (h_n[i] > cqr::kBatchMaxN || be > cqr::kBatchMaxPanel) return CQR_ERR_UNSUPPORTED;
     n[i] = (int)h_n[i];
     b[i] = (int)be;

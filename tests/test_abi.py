@@ -94,3 +94,44 @@ def test_small_workspace_rejected(lib):
     ws = C.c_void_p(1 << 20)
     st = _lib.factor_ex(100, 10, 4, FAKE, 100, FAKE, FAKE, None, 0, FAKE, ws, need - 1)
     assert st == _lib.CQR_ERR_WORKSPACE
+
+
+def test_batched_plan_argument_errors(lib):
+    """cqr_plan_batched validates every shape before touching the device."""
+    with pytest.raises(_lib.CqrError) as e:
+        _lib.plan_batched([100, 50], [10, 60], None, _lib.SCHED_MOD)   # m < n
+    assert e.value.status == _lib.CQR_ERR_ARG
+    with pytest.raises(_lib.CqrError) as e:
+        _lib.plan_batched([1000], [200], None, _lib.SCHED_MOD)         # n > 128
+    assert e.value.status == _lib.CQR_ERR_UNSUPPORTED
+    with pytest.raises(_lib.CqrError) as e:
+        _lib.plan_batched([1000], [100], [64], _lib.SCHED_MOD)         # b > 32
+    assert e.value.status == _lib.CQR_ERR_UNSUPPORTED
+    with pytest.raises(_lib.CqrError) as e:
+        _lib.plan_batched([1000], [100], None, _lib.SCHED_ORIG)        # MOD only
+    assert e.value.status == _lib.CQR_ERR_UNSUPPORTED
+    with pytest.raises(_lib.CqrError) as e:
+        _lib.plan_batched([1000], [100], [-1], _lib.SCHED_MOD)
+    assert e.value.status == _lib.CQR_ERR_ARG
+    assert _lib.lib().cqr_factor_batched(None, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.CQR_ERR_ARG
+
+
+@pytest.mark.parametrize("args,expect", [
+    ((0, 100, 10, FAKE, None, 100, 1000, FAKE, FAKE, FAKE, FAKE), _lib.CQR_ERR_ARG),  # batch < 1
+    ((1, 5, 10, FAKE, None, 100, 1000, FAKE, FAKE, FAKE, FAKE), _lib.CQR_ERR_ARG),    # m < n
+    ((2, 100, 10, FAKE, None, 100, 999, FAKE, FAKE, FAKE, FAKE), _lib.CQR_ERR_ARG),   # stride < lda n
+    ((1, 100, 10, None, None, 100, 1000, FAKE, FAKE, FAKE, FAKE), _lib.CQR_ERR_ARG),  # no Q and no A
+    ((1, 100, 10, FAKE, None, 100, 1000, None, FAKE, FAKE, FAKE), _lib.CQR_ERR_ARG),  # no R
+    ((1, 1000, 200, FAKE, None, 1000, 200000, FAKE, FAKE, FAKE, FAKE), _lib.CQR_ERR_UNSUPPORTED),
+])
+def test_backward_argument_errors(lib, args, expect):
+    bsz, m, n, q, a, lda, stride, r, dq, dr, da = args
+    ws = C.c_void_p(1 << 20)
+    st = _lib.backward_batched(bsz, m, n, q, a, lda, stride, r, dq, dr, da, None, ws, 1 << 30)
+    assert st == expect
+
+
+def test_backward_workspace_query(lib):
+    assert _lib.backward_workspace_bytes(262144, 128, 1) > 0
+    assert _lib.backward_workspace_bytes(32768, 64, 64) > _lib.backward_workspace_bytes(32768, 64, 1)
+    assert _lib.backward_workspace_bytes(10, 20, 1) == 0

@@ -93,7 +93,7 @@ def test_batched_graph_replays_match_eager():
 
 def test_batched_workload_shape_sample():
     """The 512-matrix workload's shape distribution (m in [2048, 65536], n in
-    {16, 32, 64, 128}, b = min(n, 32), log10 kappa in [2, 14]): every matrix
+    {16, 32, 64, 128}, b = min(ceil(n/2), 32), log10 kappa in [2, 14]): every matrix
     meets the accuracy bounds (measured on the device), a sample matches the
     oracle."""
     probs = matgen.batch_problems()

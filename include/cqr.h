@@ -185,7 +185,8 @@ enum cqr_kernel_kind {
   CQR_K_CHOL = 5,     /* b x b Cholesky + triangular inverse, one workgroup */
   CQR_K_SMALL = 6,    /* small R-block products and fills */
   CQR_K_BATCHED = 7,  /* the persistent batched factorisation (whole launch) */
-  CQR_K_COUNT = 8
+  CQR_K_COPY = 8,     /* copies into and out of the staging buffer */
+  CQR_K_COUNT = 9
 };
 int cqr_profile_enable(int on);
 int cqr_profile_reset(void);

@@ -66,6 +66,16 @@ def test_matrix(m: int, n: int, kappa: float, seed: int) -> np.ndarray:
     return np.asfortranarray(a)
 
 
+def gaussian_device(m: int, n: int, seed: int, device="cuda"):
+    """Column-major m x n matrix of i.i.d. N(0,1) entries from torch's device
+    RNG (no factorisation involved); well conditioned for m >> n."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed_sequence(seed, m, n, 7).generate_state(1, np.uint64)[0]) & ((1 << 63) - 1))
+    return torch.randn((n, m), dtype=torch.float64, device=device, generator=gen).t()
+
+
 def test_matrix_device(m: int, n: int, kappa: float, seed: int, device="cuda",
                        chunk_rows: int = 1 << 16):
     """Same recipe on a torch device; returns a column-major (m, n) view.

@@ -110,6 +110,10 @@ hipError_t launch_zero(double *p, int64_t count, hipStream_t s);
 hipError_t launch_zero2d(double *p, int64_t rows, int64_t cols, int64_t ld, int64_t sb, int batch,
                          hipStream_t s);
 
+// dst[0:m, c] = src[0:m, c] for c < n (column-major, leading dims lds / ldd)
+hipError_t launch_copy_cols(int64_t m, int64_t n, const double *src, int64_t lds, double *dst,
+                            int64_t ldd, hipStream_t s);
+
 // *p = v (a kernel, not a memset, so that it is safe inside captured graphs)
 hipError_t launch_set_int(int *p, int v, hipStream_t s);
 

@@ -27,6 +27,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -202,25 +204,28 @@ hipError_t launch_tn(bool gram, int64_t m, int p, int q, const double *L, int64_
 }
 
 // ----------------------------------------------------------------------------
-// k_nn: row-streaming product C = L Y (+ C), one wave per 64 x 64 tile of C.
-// The trailing update C -= Q Y is run as C + Q (-Y): the reduction that
+// k_nn: row-streaming product C = L Y (+ C), one wave per (16 RB) x 64 tile
+// of C. The trailing update C -= Q Y is run as C + Q (-Y): the reduction that
 // produces Y also stores its negation, so the hot loop feeds loaded values
-// straight to the MFMAs. A workgroup holds 4 waves arranged WR x WC (WR * WC = 4) over rows x
-// columns, so narrow products (the b-column Q_j = X U^{-1}) still keep all
-// four waves busy. Lane/element maps (cl = lane % 16, g = lane / 16):
-//   B operand, block y: lane holds L[r0 + 4 cl + y][k],  k = kk + g
+// straight to the MFMAs. A workgroup holds 4 waves arranged WR x WC
+// (WR * WC = 4) over rows x columns, so narrow products (the b-column
+// Q_j = X U^{-1}) still keep all four waves busy. Lane/element maps
+// (cl = lane % 16, g = lane / 16, y < RB row blocks, x < 4 column blocks):
+//   B operand, block y: lane holds L[r0 + RB cl + y][k],  k = kk + g
 //   A operand, block x: lane holds Y[k][c0 + 4 cl + x]
-//   D element e of block (x, y): C[r0 + 4 cl + y][c0 + 4 g + 16 e + x]
-// so that every lane's L, Y and C accesses are 4 consecutive doubles (32 B)
-// and 16 lanes cover 64 consecutive rows (or columns) of one line.
+//   D element e of block (x, y): C[r0 + RB cl + y][c0 + 4 g + 16 e + x]
+// so that every lane's L and C accesses are RB consecutive doubles and its Y
+// accesses 4 consecutive doubles, and 16 lanes cover whole lines.
+// RB = 2 (32-row tiles) halves the accumulators so that two waves fit on a
+// SIMD: one wave's loads of C and its stores overlap the other's MFMAs.
 // ----------------------------------------------------------------------------
-template <bool SUB, bool TRI, bool VEC>
-__global__ __launch_bounds__(256) void k_nn(int64_t m, int p, int q, const double *L, int64_t ldl,
-                                            const double *L2, int64_t ldl2, int psplit,
-                                            const double *__restrict__ Y, int64_t ldy,
-                                            const double *Cin, int64_t ldci, double *C, int64_t ldc,
-                                            int wr, int ncg, int64_t sL, int64_t sL2, int64_t sY,
-                                            int64_t sCin, int64_t sC, const int *__restrict__ info) {
+template <bool SUB, bool TRI, bool VEC, int RB>
+__global__ __launch_bounds__(256, (RB == 2) ? 2 : 1) void k_nn(
+    int64_t m, int p, int q, const double *L, int64_t ldl, const double *L2, int64_t ldl2,
+    int psplit, const double *__restrict__ Y, int64_t ldy, const double *Cin, int64_t ldci,
+    double *C, int64_t ldc, int wr, int ncg, int64_t sL, int64_t sL2, int64_t sY, int64_t sCin,
+    int64_t sC, const int *__restrict__ info) {
+  constexpr int kRows = 16 * RB;  // rows of a wave's tile
   if (*info) return;
   {  // batch: one matrix per grid row
     const int64_t bi = blockIdx.y;
@@ -233,18 +238,33 @@ __global__ __launch_bounds__(256) void k_nn(int64_t m, int p, int q, const doubl
   const int64_t lid = xcd_logical(blockIdx.x, gridDim.x);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
   const int wc = 4 / wr;
-  const int64_t r0 = (lid / ncg * wr + wave % wr) * (int64_t)kTile;
+  const int64_t r0 = (lid / ncg * wr + wave % wr) * (int64_t)kRows;
   const int c0 = ((int)(lid % ncg) * wc + wave / wr) * kTile;
   const bool active = c0 < q && r0 < m;
-  const int64_t rl = r0 + 4 * cl;  // first of this lane's 4 rows
-  const int yc = c0 + 4 * cl;      // first of this lane's 4 columns
+  const int64_t rl = r0 + RB * cl;  // first of this lane's RB rows
+  const int yc = c0 + 4 * cl;       // first of this lane's 4 columns
 
-  d4 acc[4][4];  // [column block x][row block y]
+  // RB consecutive doubles at p (16-byte aligned when VEC) into v[0..RB)
+  auto ld_rows = [&](const double *pp, double *v) {
+    if (VEC) {
+#pragma unroll
+      for (int h = 0; h < RB / 2; ++h) {
+        const double2 t = reinterpret_cast<const double2 *>(pp)[h];
+        v[2 * h] = t.x;
+        v[2 * h + 1] = t.y;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < RB; ++u) v[u] = pp[u];
+    }
+  };
+
+  d4 acc[4][RB];  // [column block x][row block y]
   if (active) {
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int y = 0; y < RB; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
     if (SUB) {
 #pragma unroll
       for (int e = 0; e < 4; ++e)
@@ -253,16 +273,14 @@ __global__ __launch_bounds__(256) void k_nn(int64_t m, int p, int q, const doubl
           const int col = c0 + 4 * g + 16 * e + x;
           if (col < q) {
             const double *pc = Cin + (int64_t)col * ldci + rl;
-            if (VEC && rl + 4 <= m) {
-              const double2 v0 = reinterpret_cast<const double2 *>(pc)[0];
-              const double2 v1 = reinterpret_cast<const double2 *>(pc)[1];
-              acc[x][0][e] = v0.x;
-              acc[x][1][e] = v0.y;
-              acc[x][2][e] = v1.x;
-              acc[x][3][e] = v1.y;
+            if (rl + RB <= m) {
+              double v[RB];
+              ld_rows(pc, v);
+#pragma unroll
+              for (int y = 0; y < RB; ++y) acc[x][y][e] = v[y];
             } else {
 #pragma unroll
-              for (int y = 0; y < 4; ++y) acc[x][y][e] = (rl + y < m) ? pc[y] : 0.0;
+              for (int y = 0; y < RB; ++y) acc[x][y][e] = (rl + y < m) ? pc[y] : 0.0;
             }
           }
         }
@@ -270,16 +288,16 @@ __global__ __launch_bounds__(256) void k_nn(int64_t m, int p, int q, const doubl
 
     // k range: all of p, or (upper-triangular Y) only k < c0 + 64
     const int kend = TRI ? ((c0 + kTile < p) ? c0 + kTile : p) : p;
-    // Fast path: the wave's 64 rows all exist and each lane's 4 columns are
+    // Fast path: the wave's rows all exist and each lane's 4 columns are
     // either all < q or all >= q. A lane whose columns are all >= q reads
     // column 0 instead of being masked: its operand only reaches outputs that
     // are never stored. Everything else (the last, partial row tile; q not a
     // multiple of 4 at the right edge) takes the masked loop below.
-    const bool fast = (r0 + kTile <= m) && ((q % 4) == 0 || c0 + kTile <= q);
+    const bool fast = (r0 + kRows <= m) && ((q % 4) == 0 || c0 + kTile <= q);
     const double *lb = L + rl;
     const double *lb2 = L2 + rl;  // k >= psplit reads L2[:, k - psplit]
     const double *yb = Y + (yc < q ? yc : 0);
-    auto load = [&](double (&da)[4][4], double (&db)[4][4], int kk) {
+    auto load = [&](double (&da)[4][4], double (&db)[4][RB], int kk) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int k = kk + 4 * s + g;
@@ -288,35 +306,27 @@ __global__ __launch_bounds__(256) void k_nn(int64_t m, int p, int q, const doubl
         if (VEC) {
           const double2 y0 = reinterpret_cast<const double2 *>(py)[0];
           const double2 y1 = reinterpret_cast<const double2 *>(py)[1];
-          const double2 l0 = reinterpret_cast<const double2 *>(pl)[0];
-          const double2 l1 = reinterpret_cast<const double2 *>(pl)[1];
           da[s][0] = y0.x;
           da[s][1] = y0.y;
           da[s][2] = y1.x;
           da[s][3] = y1.y;
-          db[s][0] = l0.x;
-          db[s][1] = l0.y;
-          db[s][2] = l1.x;
-          db[s][3] = l1.y;
         } else {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            da[s][u] = py[u];
-            db[s][u] = pl[u];
-          }
+          for (int u = 0; u < 4; ++u) da[s][u] = py[u];
         }
+        ld_rows(pl, db[s]);
       }
     };
-    auto compute = [&](const double (&da)[4][4], const double (&db)[4][4]) {
+    auto compute = [&](const double (&da)[4][4], const double (&db)[4][RB]) {
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x4(da[s][x], db[s][y], acc[x][y]);
+          for (int y = 0; y < RB; ++y) acc[x][y] = mfma16x16x4(da[s][x], db[s][y], acc[x][y]);
     };
     // three-deep register ring, as in k_tn
-    double a0[4][4], b0[4][4], a1[4][4], b1[4][4], a2[4][4], b2[4][4];
+    double a0[4][4], b0[4][RB], a1[4][4], b1[4][RB], a2[4][4], b2[4][RB];
     const int nit = fast ? kend / 16 : 0;  // full 16-wide k iterations
     if (nit > 0) {
       auto at = [&](int st) -> int { return 16 * (st < nit ? st : nit - 1); };
@@ -346,12 +356,11 @@ __global__ __launch_bounds__(256) void k_nn(int64_t m, int p, int q, const doubl
       for (int s = 0; s < 4; ++s) {
         const int k = kk + 4 * s + g;
         const bool kok = k < kend;
+        const double *lk = (k < psplit) ? L + (int64_t)k * ldl : L2 + (int64_t)(k - psplit) * ldl2;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          a0[s][u] = (kok && yc + u < q) ? Y[(int64_t)k * ldy + yc + u] : 0.0;
-          const double *lk = (k < psplit) ? L + (int64_t)k * ldl : L2 + (int64_t)(k - psplit) * ldl2;
-          b0[s][u] = (kok && rl + u < m) ? lk[rl + u] : 0.0;
-        }
+        for (int u = 0; u < 4; ++u) a0[s][u] = (kok && yc + u < q) ? Y[(int64_t)k * ldy + yc + u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < RB; ++u) b0[s][u] = (kok && rl + u < m) ? lk[rl + u] : 0.0;
       }
       compute(a0, b0);
     }
@@ -365,17 +374,21 @@ __global__ __launch_bounds__(256) void k_nn(int64_t m, int p, int q, const doubl
       const int col = c0 + 4 * g + 16 * e + x;
       if (col < q) {
         double *pc = C + (int64_t)col * ldc + rl;
-        if (VEC && rl + 4 <= m) {
-          reinterpret_cast<double2 *>(pc)[0] = double2{acc[x][0][e], acc[x][1][e]};
-          reinterpret_cast<double2 *>(pc)[1] = double2{acc[x][2][e], acc[x][3][e]};
+        if (VEC && rl + RB <= m) {
+#pragma unroll
+          for (int h = 0; h < RB / 2; ++h)
+            reinterpret_cast<double2 *>(pc)[h] = double2{acc[x][2 * h][e], acc[x][2 * h + 1][e]};
         } else {
 #pragma unroll
-          for (int y = 0; y < 4; ++y)
+          for (int y = 0; y < RB; ++y)
             if (rl + y < m) pc[y] = acc[x][y][e];
         }
       }
     }
 }
+
+// rows of C per workgroup row-slab is 16 * RB * WR
+constexpr int kNnRB = 2;
 
 hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const double *L,
                      int64_t ldl, const double *Y, int64_t ldy, const double *Cin, int64_t ldci,
@@ -398,16 +411,17 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
   const int wr = 4 / wc;
   const int ncg = (slabs + wc - 1) / wc;
   if (!subtract && ncg != 1) return hipErrorInvalidValue;  // in-place needs one column group
-  const int64_t rts = (m + (int64_t)kTile * wr - 1) / ((int64_t)kTile * wr);
+  const int64_t rows = 16 * kNnRB * (int64_t)wr;
+  const int64_t rts = (m + rows - 1) / rows;
   const bool vec = (ldl % 2 == 0) && (ldl2 % 2 == 0) && (ldc % 2 == 0) && (ldci % 2 == 0) &&
                    (ldy % 2 == 0) && ((uintptr_t)L % 16 == 0) && ((uintptr_t)L2 % 16 == 0) &&
                    ((uintptr_t)C % 16 == 0) && ((uintptr_t)Cin % 16 == 0) &&
                    ((uintptr_t)Y % 16 == 0) && (sL % 2 == 0) && (sL2 % 2 == 0) && (sY % 2 == 0) &&
                    (sCin % 2 == 0) && (sC % 2 == 0);
   dim3 grid((unsigned)(rts * ncg), (unsigned)batch), block(256);
-#define CQR_NN(S, T, V)                                                                          \
-  hipLaunchKernelGGL((k_nn<S, T, V>), grid, block, 0, s, m, p, q, L, ldl, L2, ldl2, psplit, Y, ldy, \
-                     Cin, ldci, C, ldc, wr, ncg, sL, sL2, sY, sCin, sC, info)
+#define CQR_NN(S, T, V)                                                                             \
+  hipLaunchKernelGGL((k_nn<S, T, V, kNnRB>), grid, block, 0, s, m, p, q, L, ldl, L2, ldl2, psplit, \
+                     Y, ldy, Cin, ldci, C, ldc, wr, ncg, sL, sL2, sY, sCin, sC, info)
   if (subtract) {
     if (vec) CQR_NN(true, false, true); else CQR_NN(true, false, false);
   } else if (upper_y) {
@@ -830,6 +844,44 @@ hipError_t launch_zero2d(double *p, int64_t rows, int64_t cols, int64_t ld, int6
 }
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
+
+// dst[:, c] = src[:, c] for the n columns of an m-row column-major block;
+// each thread moves 4 consecutive doubles (two 16-byte accesses when VEC)
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_copy_cols(int64_t m, int64_t n, const double *__restrict__ src,
+                                                   int64_t lds, double *__restrict__ dst, int64_t ldd) {
+  const int64_t step = (int64_t)gridDim.x * 256 * 4;
+  for (int64_t c = blockIdx.y; c < n; c += gridDim.y) {
+    const double *s = src + c * lds;
+    double *d = dst + c * ldd;
+    for (int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4; i < m; i += step) {
+      if (VEC && i + 4 <= m) {
+        const double2 a = reinterpret_cast<const double2 *>(s + i)[0];
+        const double2 b = reinterpret_cast<const double2 *>(s + i)[1];
+        reinterpret_cast<double2 *>(d + i)[0] = a;
+        reinterpret_cast<double2 *>(d + i)[1] = b;
+      } else {
+        for (int k = 0; k < 4 && i + k < m; ++k) d[i + k] = s[i + k];
+      }
+    }
+  }
+}
+
+hipError_t launch_copy_cols(int64_t m, int64_t n, const double *src, int64_t lds, double *dst,
+                            int64_t ldd, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int64_t bx = std::min<int64_t>((m + 1023) / 1024, 256);
+  const int64_t by = std::min<int64_t>(n, 4096);
+  const bool vec = (lds % 2 == 0) && (ldd % 2 == 0) && ((uintptr_t)src % 16 == 0) &&
+                   ((uintptr_t)dst % 16 == 0);
+  if (vec)
+    hipLaunchKernelGGL(k_copy_cols<true>, dim3((unsigned)bx, (unsigned)by), dim3(256), 0, s, m, n,
+                       src, lds, dst, ldd);
+  else
+    hipLaunchKernelGGL(k_copy_cols<false>, dim3((unsigned)bx, (unsigned)by), dim3(256), 0, s, m, n,
+                       src, lds, dst, ldd);
+  return hipGetLastError();
+}
 
 hipError_t launch_set_int(int *p, int v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v);

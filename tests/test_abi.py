@@ -56,6 +56,11 @@ def test_workspace_and_panel_queries(lib):
     # ORIG keeps R1 and R2: more workspace than MOD
     assert (_lib.workspace_bytes(1 << 20, 256, 64, _lib.SCHED_ORIG)
             > _lib.workspace_bytes(1 << 20, 256, 64, _lib.SCHED_MOD))
+    # a row count whose natural stride is a multiple of 1024 doubles adds the
+    # staging copy (one shifted-stride m x n buffer) to the workspace
+    extra = (_lib.workspace_bytes(8192, 96, 32, _lib.SCHED_MOD)
+             - _lib.workspace_bytes(8208, 96, 32, _lib.SCHED_MOD))
+    assert 8 * 8208 * 96 <= extra < 8 * 8208 * 96 + 512
     for n in (1, 16, 64, 100, 256, 1024):
         for s in (_lib.SCHED_MOD, _lib.SCHED_ORIG):
             b = _lib.default_panel(1 << 20, n, s)

@@ -100,6 +100,30 @@ def test_deterministic_and_in_place():
 
 
 @pytest.mark.parametrize("sched", ["orig", "mod"])
+def test_aliasing_stride_staged_bitwise(sched):
+    """lda a multiple of 1024 doubles is factored in a staging copy with a
+    shifted stride. The split-m plan depends on m only, so Q and R equal the
+    in-place runs (lda + 16; a caller workspace without room for the copy)
+    bit for bit, and meet the oracle bounds."""
+    m, n, b, kappa = 8192, 96, 32, 1e10
+    a = matgen.test_matrix(m, n, kappa, seed=8)
+    q1, r1 = _factor(a, b, sched)                 # lda = 8192: staged
+    q2, r2 = _factor(a, b, sched, ld=m + 16)      # in place
+    assert np.array_equal(q1, q2) and np.array_equal(r1, r2)
+    ad = to_dev(a)
+    small = cqr.Workspace(m + 16, n, b, sched, ad.device)   # no staging room for m
+    assert small.bytes < cqr._lib.workspace_bytes(m, n, b, cqr.SCHEDULES[sched])
+    q3, r3 = cqr.qr(ad, b=b, schedule=sched, workspace=small)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(q3), q1) and np.array_equal(to_host(r3), r1)
+    fo = oracle.mcqr2gs if sched == "mod" else oracle.cqr2gs
+    qo, ro = fo(a, b)
+    assert oracle.orthogonality(q1) <= 1e-13
+    assert oracle.residual(a, q1, r1) <= 1e-14
+    assert oracle.rel_fro(r1, ro) <= 100 * n * U * kappa
+
+
+@pytest.mark.parametrize("sched", ["orig", "mod"])
 @pytest.mark.parametrize("col", [0, 11, 31])
 def test_breakdown_column(sched, col):
     """An exactly zero column stays zero through every projection and update

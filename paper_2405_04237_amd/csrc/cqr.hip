@@ -145,6 +145,8 @@ struct Run {
   int64_t m, n;
   double *W, *Uinv, *Ua, *Ub, *Y, *part, *R1, *R2;
   int64_t part_elems;
+  double *Qout;  // staged runs: the caller's Q, written by each panel's final step
+  int64_t ldq;
 };
 
 void plan_chunks(const Run &r, int64_t tiles, int64_t pq, int64_t *rc, int64_t *nch) {
@@ -185,11 +187,14 @@ hipError_t step_chol(Run &r, int w, double *uout, double *rblk, int64_t ldr, int
   });
 }
 
-// Q = X U^{-1} (the Q_j := A_j U^{-1} step); Q may be X (in place)
-hipError_t step_trsm(Run &r, const double *X, double *Qo, int64_t ld, int w) {
-  return timed(r.s, CQR_K_TRSM, double(r.m) * w * w, 16.0 * r.m * w, [&] {
+// Q = X U^{-1} (the Q_j := A_j U^{-1} step); Q may be X (in place). col >= 0
+// marks the panel's final Q, which a staged run also writes to the caller's
+// Q at that column.
+hipError_t step_trsm(Run &r, const double *X, double *Qo, int64_t ld, int w, int64_t col = -1) {
+  double *q2 = (col >= 0 && r.Qout) ? r.Qout + col * r.ldq : nullptr;
+  return timed(r.s, CQR_K_TRSM, double(r.m) * w * w, (q2 ? 24.0 : 16.0) * r.m * w, [&] {
     return cqr::launch_nn(false, true, r.m, w, w, X, ld, r.Uinv, cqr::padded_ld(w), nullptr, ld, Qo,
-                          ld, r.info, r.s);
+                          ld, r.info, r.s, nullptr, 0, 0, 1, 0, 0, 0, 0, 0, q2, r.ldq);
   });
 }
 
@@ -221,7 +226,8 @@ hipError_t step_update(Run &r, const double *Qp, int64_t ld, int p, const double
 // split-m reductions), writing Q into X and its R into Rd (n x n, ld n).
 // Columns not yet produced are read from src (A on the first pass, so that
 // A is never copied or written); src may equal X.
-hipError_t pass_cqrgs(Run &r, const double *src, double *X, int64_t ld, int64_t b, double *Rd) {
+hipError_t pass_cqrgs(Run &r, const double *src, double *X, int64_t ld, int64_t b, double *Rd,
+                      bool final) {
   const int64_t n = r.n;
   for (int64_t s = 0; s < n; s += b) {
     const int64_t e = std::min(n, s + b);
@@ -231,7 +237,7 @@ hipError_t pass_cqrgs(Run &r, const double *src, double *X, int64_t ld, int64_t 
     const double *Ar = (s == 0) ? src + e * ld : X + e * ld;         // trailing panels
     CQR_TRY(step_gram(r, Aj, ld, w));                                // W_j := A_j^T A_j
     CQR_TRY(step_chol(r, w, nullptr, Rd + s + s * n, n, (int)s));    // W_j = U^T U; R_jj := U
-    CQR_TRY(step_trsm(r, Aj, Xj, ld, w));                            // Q_j := A_j U^{-1}
+    CQR_TRY(step_trsm(r, Aj, Xj, ld, w, final ? s : -1));            // Q_j := A_j U^{-1}
     if (e < n) {
       CQR_TRY(step_proj(r, Xj, ld, w, Ar, (int)(n - e), Rd + s + e * n, n));  // Y; R_{j,j+1:k}
       CQR_TRY(step_update(r, Xj, ld, w, Ar, X + e * ld, (int)(n - e)));       // A_{j+1:k} -= Q_j Y
@@ -244,8 +250,8 @@ hipError_t run_orig(Run &r, const double *A, double *Q, int64_t ld, int64_t b, d
   const int64_t n = r.n;
   CQR_TRY(timed(r.s, CQR_K_SMALL, 0, 16.0 * n * n, [&] { return cqr::launch_zero(r.R1, n * n, r.s); }));
   CQR_TRY(timed(r.s, CQR_K_SMALL, 0, 16.0 * n * n, [&] { return cqr::launch_zero(r.R2, n * n, r.s); }));
-  CQR_TRY(pass_cqrgs(r, A, Q, ld, b, r.R1));  // [Q1, R1] = CQRGS(A)
-  CQR_TRY(pass_cqrgs(r, Q, Q, ld, b, r.R2));  // [Q, R2]  = CQRGS(Q1)
+  CQR_TRY(pass_cqrgs(r, A, Q, ld, b, r.R1, false));  // [Q1, R1] = CQRGS(A)
+  CQR_TRY(pass_cqrgs(r, Q, Q, ld, b, r.R2, true));   // [Q, R2]  = CQRGS(Q1)
   const double nf = n;
   return timed(r.s, CQR_K_SMALL, nf * nf * nf / 3.0, 24.0 * nf * nf, [&] {
     return cqr::launch_trmm_upper((int)n, r.R2, r.R1, R, r.info, r.s);  // R = R2 R1
@@ -263,7 +269,7 @@ hipError_t run_mod(Run &r, const double *A, double *Q, int64_t ld, int64_t b, do
     CQR_TRY(step_trsm(r, A, Q, ld, w));
     CQR_TRY(step_gram(r, Q, ld, w));
     CQR_TRY(step_chol(r, w, r.Ub, nullptr, 0, 0));
-    CQR_TRY(step_trsm(r, Q, Q, ld, w));
+    CQR_TRY(step_trsm(r, Q, Q, ld, w, 0));
     CQR_TRY(timed(r.s, CQR_K_SMALL, 0, 0, [&] {
       return cqr::launch_r_upper_product(w, r.Ub, r.Ua, R, n, r.info, r.s);  // R_11 = R2 R1
     }));
@@ -291,7 +297,7 @@ hipError_t run_mod(Run &r, const double *A, double *Q, int64_t ld, int64_t b, do
     // CQR again: Qt = Q_j Ub; R_jj = Ub Ua
     CQR_TRY(step_gram(r, Xj, ld, w));
     CQR_TRY(step_chol(r, w, r.Ub, nullptr, 0, (int)s));
-    CQR_TRY(step_trsm(r, Xj, Xj, ld, w));
+    CQR_TRY(step_trsm(r, Xj, Xj, ld, w, s));
     CQR_TRY(timed(r.s, CQR_K_SMALL, 0, 0, [&] {
       return cqr::launch_r_upper_product(w, r.Ub, r.Ua, R + s + s * n, n, r.info, r.s);
     }));
@@ -449,14 +455,15 @@ int cqr_factor_ex(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
     return CQR_ERR_HIP;
   hipError_t e;
   if (lay.stage >= 0) {
+    // factor in the staging copy; each panel's final Q_j goes to both copies
     double *S = (double *)(ws + lay.stage);
     const int64_t ldw = lay.ldw;
-    const double mb = 16.0 * m * n;
-    e = timed(s, CQR_K_COPY, 0, mb, [&] { return cqr::launch_copy_cols(m, n, A, lda, S, ldw, s); });
+    r.Qout = Q;
+    r.ldq = lda;
+    e = timed(s, CQR_K_COPY, 0, 16.0 * m * n,
+              [&] { return cqr::launch_copy_cols(m, n, A, lda, S, ldw, s); });
     if (e == hipSuccess)
       e = (schedule == CQR_SCHED_ORIG) ? run_orig(r, S, S, ldw, be, R) : run_mod(r, S, S, ldw, be, R);
-    if (e == hipSuccess)
-      e = timed(s, CQR_K_COPY, 0, mb, [&] { return cqr::launch_copy_cols(m, n, S, ldw, Q, lda, s); });
   } else {
     e = (schedule == CQR_SCHED_ORIG) ? run_orig(r, A, Q, lda, be, R) : run_mod(r, A, Q, lda, be, R);
   }

@@ -38,12 +38,14 @@ int64_t tn_tiles(bool gram, int p, int q);
 // L2/ldl2/psplit: optional second left operand; rows k >= psplit of Y
 // multiply columns k - psplit of L2, i.e. the left operand is
 // [L(:, 0:psplit) | L2]. L2 = nullptr means L alone.
+// C2/ldc2 (subtract = false, batch = 1 only): a second destination that
+// receives the same values as C.
 hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const double *L,
                      int64_t ldl, const double *Y, int64_t ldy, const double *Cin, int64_t ldci,
                      double *C, int64_t ldc, const int *info, hipStream_t s,
                      const double *L2 = nullptr, int64_t ldl2 = 0, int psplit = 0, int batch = 1,
                      int64_t sL = 0, int64_t sL2 = 0, int64_t sY = 0, int64_t sCin = 0,
-                     int64_t sC = 0);
+                     int64_t sC = 0, double *C2 = nullptr, int64_t ldc2 = 0);
 
 // Leading dimension used for row-major p x q operands written by the
 // library (a multiple of 4 doubles, so rows stay 32-byte aligned).

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256, (RB == 2) ? 2 : 1) void k_nn(
     int64_t m, int p, int q, const double *L, int64_t ldl, const double *L2, int64_t ldl2,
     int psplit, const double *__restrict__ Y, int64_t ldy, const double *Cin, int64_t ldci,
     double *C, int64_t ldc, int wr, int ncg, int64_t sL, int64_t sL2, int64_t sY, int64_t sCin,
-    int64_t sC, const int *__restrict__ info) {
+    int64_t sC, double *C2, int64_t ldc2, const int *__restrict__ info) {
   constexpr int kRows = 16 * RB;  // rows of a wave's tile
   if (*info) return;
   {  // batch: one matrix per grid row
@@ -374,17 +374,173 @@ __global__ __launch_bounds__(256, (RB == 2) ? 2 : 1) void k_nn(
       const int col = c0 + 4 * g + 16 * e + x;
       if (col < q) {
         double *pc = C + (int64_t)col * ldc + rl;
+        double *pc2 = C2 ? C2 + (int64_t)col * ldc2 + rl : nullptr;
         if (VEC && rl + RB <= m) {
 #pragma unroll
-          for (int h = 0; h < RB / 2; ++h)
-            reinterpret_cast<double2 *>(pc)[h] = double2{acc[x][2 * h][e], acc[x][2 * h + 1][e]};
+          for (int h = 0; h < RB / 2; ++h) {
+            const double2 v = double2{acc[x][2 * h][e], acc[x][2 * h + 1][e]};
+            reinterpret_cast<double2 *>(pc)[h] = v;
+            if (pc2) reinterpret_cast<double2 *>(pc2)[h] = v;
+          }
         } else {
 #pragma unroll
           for (int y = 0; y < RB; ++y)
-            if (rl + y < m) pc[y] = acc[x][y][e];
+            if (rl + y < m) {
+              pc[y] = acc[x][y][e];
+              if (pc2) pc2[y] = acc[x][y][e];
+            }
         }
       }
     }
+}
+
+// ----------------------------------------------------------------------------
+// k_upd: the trailing update C = Cin + L Y for a short inner dimension
+// (p <= kUpdMaxK, the panel width): Y is p x q and is re-read for every row
+// tile by k_nn, which makes that kernel bound by L2 -> CU traffic. Here a
+// workgroup owns one 64-column slab of C and a contiguous range of rows; it
+// stages its slab of Y (zero-padded to a multiple of 16 rows) in LDS once and
+// its four waves sweep 32-row tiles of the range, reading only L, Cin and C
+// from global memory. Lane/element maps are those of k_nn with RB = 2.
+// Consecutive logical workgroups share a row range (and so L's rows in one
+// XCD's L2) and differ in the slab.
+// ----------------------------------------------------------------------------
+constexpr int kUpdMaxK = 128;
+
+__global__ __launch_bounds__(256, 2) void k_upd(int64_t m, int p, int q, const double *L,
+                                                int64_t ldl, const double *__restrict__ Y,
+                                                int64_t ldy, const double *Cin, int64_t ldci,
+                                                double *C, int64_t ldc, int nslab,
+                                                int64_t rows_per_wg, const int *__restrict__ info) {
+  extern __shared__ double ys[];  // [pp][64], row-major
+  if (*info) return;
+  const int64_t lid = xcd_logical(blockIdx.x, gridDim.x);
+  const int c0 = (int)(lid % nslab) * kTile;
+  const int64_t rb = (lid / nslab) * rows_per_wg;
+  if (rb >= m) return;  // whole workgroup
+  const int64_t re = (rb + rows_per_wg < m) ? rb + rows_per_wg : m;
+  const int pp = (p + 15) / 16 * 16;
+  for (int e = threadIdx.x; e < pp * kTile; e += 256) {
+    const int k = e / kTile, c = c0 + e % kTile;
+    ys[e] = (k < p && c < q) ? Y[(int64_t)k * ldy + c] : 0.0;
+  }
+  __syncthreads();
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const double *yl = ys + 4 * cl;  // this lane's 4 columns of the slab
+  const int nit = p / 16;  // full 16-wide k steps; a ragged p adds one masked step
+
+  for (int64_t r0 = rb + 32 * wave; r0 < re; r0 += 128) {
+    const int64_t rl = r0 + 2 * cl;
+    const bool full = r0 + 32 <= m;
+    d4 acc[4][2];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int col = c0 + 4 * g + 16 * e + x;
+        double v0 = 0.0, v1 = 0.0;
+        if (col < q) {
+          const double *pc = Cin + (int64_t)col * ldci + rl;
+          if (full) {
+            const double2 t = *reinterpret_cast<const double2 *>(pc);
+            v0 = t.x;
+            v1 = t.y;
+          } else {
+            v0 = (rl < m) ? pc[0] : 0.0;
+            v1 = (rl + 1 < m) ? pc[1] : 0.0;
+          }
+        }
+        acc[x][0][e] = v0;
+        acc[x][1][e] = v1;
+      }
+    auto load_y = [&](double (&da)[4][4], int kk) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = kk + 4 * s + g;
+        const double2 y0 = *reinterpret_cast<const double2 *>(yl + k * kTile);
+        const double2 y1 = *reinterpret_cast<const double2 *>(yl + k * kTile + 2);
+        da[s][0] = y0.x;
+        da[s][1] = y0.y;
+        da[s][2] = y1.x;
+        da[s][3] = y1.y;
+      }
+    };
+    auto compute = [&](const double (&da)[4][4], const double (&db)[4][2]) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x4(da[s][x], db[s][y], acc[x][y]);
+    };
+    // Y comes from LDS (short latency) right before its step; only L, from
+    // global memory, goes through a three-deep register ring
+    double a0[4][4], b0[4][2];
+    const double *lb = L + (int64_t)g * ldl + rl;  // column g of this lane's rows
+    if (full && nit > 0) {
+      auto load = [&](double (&db)[4][2], int kk) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double2 t = *reinterpret_cast<const double2 *>(lb + (int64_t)(kk + 4 * s) * ldl);
+          db[s][0] = t.x;
+          db[s][1] = t.y;
+        }
+      };
+      auto step = [&](const double (&db)[4][2], int kk) {
+        load_y(a0, kk);
+        compute(a0, db);
+      };
+      double b1[4][2], b2[4][2];
+      auto at = [&](int st) -> int { return 16 * (st < nit ? st : nit - 1); };
+      load(b0, 0);
+      load(b1, at(1));
+      int it = 0;
+      for (; it + 3 <= nit; it += 3) {
+        load(b2, at(it + 2));
+        __builtin_amdgcn_sched_barrier(0);
+        step(b0, 16 * it);
+        __builtin_amdgcn_sched_barrier(0);
+        load(b0, at(it + 3));
+        __builtin_amdgcn_sched_barrier(0);
+        step(b1, 16 * (it + 1));
+        __builtin_amdgcn_sched_barrier(0);
+        load(b1, at(it + 4));
+        __builtin_amdgcn_sched_barrier(0);
+        step(b2, 16 * (it + 2));
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (it < nit) step(b0, 16 * it);
+      if (it + 1 < nit) step(b1, 16 * (it + 1));
+    }
+    // masked steps: every step of the last, partial row tile; the ragged k tail
+    for (int kk = (full ? 16 * nit : 0); kk < pp; kk += 16) {
+      load_y(a0, kk);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = kk + 4 * s + g;
+        const double *pl = L + (int64_t)(k < p ? k : 0) * ldl + rl;
+        b0[s][0] = (k < p && rl < m) ? pl[0] : 0.0;
+        b0[s][1] = (k < p && rl + 1 < m) ? pl[1] : 0.0;
+      }
+      compute(a0, b0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int col = c0 + 4 * g + 16 * e + x;
+        if (col < q) {
+          double *pc = C + (int64_t)col * ldc + rl;
+          if (full) {
+            *reinterpret_cast<double2 *>(pc) = double2{acc[x][0][e], acc[x][1][e]};
+          } else {
+            if (rl < m) pc[0] = acc[x][0][e];
+            if (rl + 1 < m) pc[1] = acc[x][1][e];
+          }
+        }
+      }
+  }
 }
 
 // rows of C per workgroup row-slab is 16 * RB * WR
@@ -394,7 +550,8 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
                      int64_t ldl, const double *Y, int64_t ldy, const double *Cin, int64_t ldci,
                      double *C, int64_t ldc, const int *info, hipStream_t s, const double *L2,
                      int64_t ldl2, int psplit, int batch, int64_t sL, int64_t sL2, int64_t sY,
-                     int64_t sCin, int64_t sC) {
+                     int64_t sCin, int64_t sC, double *C2, int64_t ldc2) {
+  if (C2 && (subtract || batch != 1)) return hipErrorInvalidValue;
   if (!L2) {
     L2 = L;
     ldl2 = ldl;
@@ -411,17 +568,38 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
   const int wr = 4 / wc;
   const int ncg = (slabs + wc - 1) / wc;
   if (!subtract && ncg != 1) return hipErrorInvalidValue;  // in-place needs one column group
+  if (subtract && batch == 1 && psplit == p && p <= kUpdMaxK && (ldl % 2 == 0) &&
+      (ldc % 2 == 0) && (ldci % 2 == 0) && ((uintptr_t)L % 16 == 0) &&
+      ((uintptr_t)C % 16 == 0) && ((uintptr_t)Cin % 16 == 0)) {
+    // about four resident workgroups per CU worth of work items, 128-row multiples
+    const int64_t target = 1024;
+    int64_t rpw = (m * slabs + target - 1) / target;
+    rpw = std::max<int64_t>(128, (rpw + 127) / 128 * 128);
+    const int64_t chunks = (m + rpw - 1) / rpw;
+    const size_t lds = (size_t)((p + 15) / 16 * 16) * kTile * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+      const hipError_t e = hipFuncSetAttribute((const void *)k_upd,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               kUpdMaxK * kTile * (int)sizeof(double));
+      if (e != hipSuccess) return e;
+      attr = true;
+    }
+    hipLaunchKernelGGL(k_upd, dim3((unsigned)(chunks * slabs)), dim3(256), lds, s, m, p, q, L, ldl,
+                       Y, ldy, Cin, ldci, C, ldc, slabs, rpw, info);
+    return hipGetLastError();
+  }
   const int64_t rows = 16 * kNnRB * (int64_t)wr;
   const int64_t rts = (m + rows - 1) / rows;
   const bool vec = (ldl % 2 == 0) && (ldl2 % 2 == 0) && (ldc % 2 == 0) && (ldci % 2 == 0) &&
                    (ldy % 2 == 0) && ((uintptr_t)L % 16 == 0) && ((uintptr_t)L2 % 16 == 0) &&
                    ((uintptr_t)C % 16 == 0) && ((uintptr_t)Cin % 16 == 0) &&
                    ((uintptr_t)Y % 16 == 0) && (sL % 2 == 0) && (sL2 % 2 == 0) && (sY % 2 == 0) &&
-                   (sCin % 2 == 0) && (sC % 2 == 0);
+                   (sCin % 2 == 0) && (sC % 2 == 0) && (ldc2 % 2 == 0) && ((uintptr_t)C2 % 16 == 0);
   dim3 grid((unsigned)(rts * ncg), (unsigned)batch), block(256);
 #define CQR_NN(S, T, V)                                                                             \
   hipLaunchKernelGGL((k_nn<S, T, V, kNnRB>), grid, block, 0, s, m, p, q, L, ldl, L2, ldl2, psplit, \
-                     Y, ldy, Cin, ldci, C, ldc, wr, ncg, sL, sL2, sY, sCin, sC, info)
+                     Y, ldy, Cin, ldci, C, ldc, wr, ncg, sL, sL2, sY, sCin, sC, C2, ldc2, info)
   if (subtract) {
     if (vec) CQR_NN(true, false, true); else CQR_NN(true, false, false);
   } else if (upper_y) {
@@ -845,24 +1023,34 @@ hipError_t launch_zero2d(double *p, int64_t rows, int64_t cols, int64_t ld, int6
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
-// dst[:, c] = src[:, c] for the n columns of an m-row column-major block;
-// each thread moves 4 consecutive doubles (two 16-byte accesses when VEC)
+// dst[:, c] = src[:, c] for the n columns of an m-row column-major block.
+// A block copies 4096-row segments of one column; each thread moves 4 runs
+// of 4 consecutive doubles, all loads issued before the stores.
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_copy_cols(int64_t m, int64_t n, const double *__restrict__ src,
                                                    int64_t lds, double *__restrict__ dst, int64_t ldd) {
-  const int64_t step = (int64_t)gridDim.x * 256 * 4;
-  for (int64_t c = blockIdx.y; c < n; c += gridDim.y) {
+  const int64_t segs = (m + 4095) / 4096;
+  for (int64_t t = blockIdx.x; t < segs * n; t += gridDim.x) {
+    const int64_t c = t / segs, r0 = (t % segs) * 4096;
     const double *s = src + c * lds;
     double *d = dst + c * ldd;
-    for (int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4; i < m; i += step) {
-      if (VEC && i + 4 <= m) {
-        const double2 a = reinterpret_cast<const double2 *>(s + i)[0];
-        const double2 b = reinterpret_cast<const double2 *>(s + i)[1];
-        reinterpret_cast<double2 *>(d + i)[0] = a;
-        reinterpret_cast<double2 *>(d + i)[1] = b;
-      } else {
-        for (int k = 0; k < 4 && i + k < m; ++k) d[i + k] = s[i + k];
+    if (VEC && r0 + 4096 <= m) {
+      double2 v[8];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = r0 + 1024 * u + 4 * threadIdx.x;
+        v[2 * u] = reinterpret_cast<const double2 *>(s + i)[0];
+        v[2 * u + 1] = reinterpret_cast<const double2 *>(s + i)[1];
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = r0 + 1024 * u + 4 * threadIdx.x;
+        reinterpret_cast<double2 *>(d + i)[0] = v[2 * u];
+        reinterpret_cast<double2 *>(d + i)[1] = v[2 * u + 1];
+      }
+    } else {
+      const int64_t r1 = (r0 + 4096 < m) ? r0 + 4096 : m;
+      for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) d[i] = s[i];
     }
   }
 }
@@ -870,16 +1058,16 @@ __global__ __launch_bounds__(256) void k_copy_cols(int64_t m, int64_t n, const d
 hipError_t launch_copy_cols(int64_t m, int64_t n, const double *src, int64_t lds, double *dst,
                             int64_t ldd, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  const int64_t bx = std::min<int64_t>((m + 1023) / 1024, 256);
-  const int64_t by = std::min<int64_t>(n, 4096);
+  const int64_t work = (m + 4095) / 4096 * n;
+  const int64_t bx = std::min<int64_t>(work, 16384);
   const bool vec = (lds % 2 == 0) && (ldd % 2 == 0) && ((uintptr_t)src % 16 == 0) &&
                    ((uintptr_t)dst % 16 == 0);
   if (vec)
-    hipLaunchKernelGGL(k_copy_cols<true>, dim3((unsigned)bx, (unsigned)by), dim3(256), 0, s, m, n,
-                       src, lds, dst, ldd);
+    hipLaunchKernelGGL(k_copy_cols<true>, dim3((unsigned)bx), dim3(256), 0, s, m, n, src, lds, dst,
+                       ldd);
   else
-    hipLaunchKernelGGL(k_copy_cols<false>, dim3((unsigned)bx, (unsigned)by), dim3(256), 0, s, m, n,
-                       src, lds, dst, ldd);
+    hipLaunchKernelGGL(k_copy_cols<false>, dim3((unsigned)bx), dim3(256), 0, s, m, n, src, lds, dst,
+                       ldd);
   return hipGetLastError();
 }
 

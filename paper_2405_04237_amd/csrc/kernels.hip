@@ -543,6 +543,128 @@ __global__ __launch_bounds__(256, 2) void k_upd(int64_t m, int p, int q, const d
   }
 }
 
+// ----------------------------------------------------------------------------
+// k_trsm: Q_j = X U^{-1} in place for a panel of w = 64 or 128 columns (w a
+// multiple of 16), over the rows [0, mfull) in blocks of 32 * 8 / nslab rows.
+// One persistent 8-wave workgroup per CU keeps U^{-1} (upper triangle,
+// zero elsewhere) in LDS and takes every gridDim.x-th row block. Waves split
+// a block into 32 x 64 tiles (wave / 4 = column slab when w = 128); slab s
+// only needs rows k < 64 (s + 1) of U^{-1}. The k steps of consecutive
+// blocks form one stream through a three-deep register ring, so the next
+// block's X rows are in flight while the current block finishes; a
+// workgroup barrier between the last read of a block's X rows and the first
+// write of its Q rows keeps the in-place update safe. X2 (optional) receives
+// the same values as X.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(512, 1) void k_trsm(int64_t mfull, int w, double *X, int64_t ldx,
+                                                 const double *__restrict__ Uinv, int64_t ldu,
+                                                 double *X2, int64_t ldx2,
+                                                 const int *__restrict__ info) {
+  extern __shared__ double us[];  // [w][w] row-major
+  if (*info) return;
+  const int nslab = w / kTile;
+  for (int e = threadIdx.x; e < w * w; e += 512) {
+    const int k = e / w, c = e % w;
+    us[e] = (c >= k) ? Uinv[(int64_t)k * ldu + c] : 0.0;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const int slab = (nslab == 2) ? wave >> 2 : 0;
+  const int tile = (nslab == 2) ? wave & 3 : wave;
+  const int64_t brows = (nslab == 2) ? 128 : 256;  // rows per block
+  const int64_t nblk = mfull / brows;
+  if ((int64_t)blockIdx.x >= nblk) return;  // whole workgroup
+  const int64_t nmine = (nblk - blockIdx.x + gridDim.x - 1) / gridDim.x;
+  const int nk = (kTile * (slab + 1)) / 16;  // k steps of this wave's slab
+  const int64_t T = nmine * nk;
+  const int c0 = kTile * slab;
+  const double *yl = us + c0 + 4 * cl;
+  const int64_t rstep = (int64_t)gridDim.x * brows;  // rows between this workgroup's blocks
+  const int64_t rfirst = (int64_t)blockIdx.x * brows + 32 * tile + 2 * cl;
+
+  d4 acc[4][2];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+
+  // load cursor: step index -> pointer to X[row rl][column 16 ks + g]
+  int64_t lt = 0;
+  const double *lp = X + rfirst + (int64_t)g * ldx;
+  auto load = [&](double (&db)[4][2]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double2 t = *reinterpret_cast<const double2 *>(lp + (int64_t)(4 * s) * ldx);
+      db[s][0] = t.x;
+      db[s][1] = t.y;
+    }
+    if (lt + 1 < T) {  // advance; past the end the last step is re-read
+      ++lt;
+      lp += ((lt % nk) == 0) ? rstep - (int64_t)(nk - 1) * 16 * ldx : 16 * ldx;
+    }
+  };
+  // compute cursor
+  int ks = 0;
+  int64_t rl = rfirst;
+  double ya[4][4];
+  auto step = [&](const double (&db)[4][2]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 16 * ks + 4 * s + g;
+      const double2 y0 = *reinterpret_cast<const double2 *>(yl + k * w);
+      const double2 y1 = *reinterpret_cast<const double2 *>(yl + k * w + 2);
+      ya[s][0] = y0.x;
+      ya[s][1] = y0.y;
+      ya[s][2] = y1.x;
+      ya[s][3] = y1.y;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x4(ya[s][x], db[s][y], acc[x][y]);
+    if (++ks == nk) {  // block done: every wave has read its X rows, then write
+      ks = 0;
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const int col = c0 + 4 * g + 16 * e + x;
+          const double2 v = double2{acc[x][0][e], acc[x][1][e]};
+          *reinterpret_cast<double2 *>(X + (int64_t)col * ldx + rl) = v;
+          if (X2) *reinterpret_cast<double2 *>(X2 + (int64_t)col * ldx2 + rl) = v;
+        }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+      rl += rstep;
+    }
+  };
+  double b0[4][2], b1[4][2], b2[4][2];
+  load(b0);
+  load(b1);
+  int64_t t = 0;
+  for (; t + 3 <= T; t += 3) {
+    load(b2);
+    __builtin_amdgcn_sched_barrier(0);
+    step(b0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(b0);
+    __builtin_amdgcn_sched_barrier(0);
+    step(b1);
+    __builtin_amdgcn_sched_barrier(0);
+    load(b1);
+    __builtin_amdgcn_sched_barrier(0);
+    step(b2);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (t < T) step(b0);
+  if (t + 1 < T) step(b1);
+}
+
 // rows of C per workgroup row-slab is 16 * RB * WR
 constexpr int kNnRB = 2;
 
@@ -568,23 +690,64 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
   const int wr = 4 / wc;
   const int ncg = (slabs + wc - 1) / wc;
   if (!subtract && ncg != 1) return hipErrorInvalidValue;  // in-place needs one column group
+  if (!subtract && upper_y && batch == 1 && p == q && (q == 64 || q == 128) &&
+      m >= (q == 128 ? 128 : 256) && L == C &&
+      Cin == C && ldl == ldc && ldy == q && (ldc % 2 == 0) && ((uintptr_t)C % 16 == 0) &&
+      (!C2 || ((ldc2 % 2 == 0) && ((uintptr_t)C2 % 16 == 0)))) {
+    // in-place Q = X U^{-1}: persistent U^{-1}-in-LDS kernel over the full
+    // row blocks, k_nn for the remaining rows
+    const int64_t brows = (q == 128) ? 128 : 256;
+    const int64_t mfull = m / brows * brows;  // > 0; the k_nn call below has m < brows
+    {
+      static bool attr = false;
+      static int cus = 0;
+      if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_trsm,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kMaxPanel * kMaxPanel * (int)sizeof(double));
+        if (e != hipSuccess) return e;
+        int dev = 0;
+        e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        attr = true;
+      }
+      const int64_t nblk = mfull / brows;
+      const int64_t grid = std::min<int64_t>(nblk, std::max(cus, 1));
+      hipLaunchKernelGGL(k_trsm, dim3((unsigned)grid), dim3(512),
+                         (size_t)q * q * sizeof(double), s, mfull, q, C, ldc, Y, ldy, C2, ldc2,
+                         info);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess || mfull == m) return e;
+    }
+    return launch_nn(false, true, m - mfull, p, q, L + mfull, ldl, Y, ldy, nullptr, 0, C + mfull,
+                     ldc, info, s, nullptr, 0, 0, 1, 0, 0, 0, 0, 0, C2 ? C2 + mfull : nullptr, ldc2);
+  }
   if (subtract && batch == 1 && psplit == p && p <= kUpdMaxK && (ldl % 2 == 0) &&
       (ldc % 2 == 0) && (ldci % 2 == 0) && ((uintptr_t)L % 16 == 0) &&
       ((uintptr_t)C % 16 == 0) && ((uintptr_t)Cin % 16 == 0)) {
-    // about four resident workgroups per CU worth of work items, 128-row multiples
-    const int64_t target = 1024;
-    int64_t rpw = (m * slabs + target - 1) / target;
-    rpw = std::max<int64_t>(128, (rpw + 127) / 128 * 128);
-    const int64_t chunks = (m + rpw - 1) / rpw;
-    const size_t lds = (size_t)((p + 15) / 16 * 16) * kTile * sizeof(double);
+    // one round of resident workgroups (two per CU): each slab gets an equal
+    // share of them, each with an equal range of rows (a multiple of 32)
     static bool attr = false;
+    static int cus = 0;
     if (!attr) {
-      const hipError_t e = hipFuncSetAttribute((const void *)k_upd,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               kUpdMaxK * kTile * (int)sizeof(double));
+      hipError_t e = hipFuncSetAttribute((const void *)k_upd,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         kUpdMaxK * kTile * (int)sizeof(double));
+      if (e != hipSuccess) return e;
+      int dev = 0;
+      e = hipGetDevice(&dev);
+      if (e != hipSuccess) return e;
+      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
       if (e != hipSuccess) return e;
       attr = true;
     }
+    const int64_t per_slab = std::max<int64_t>(1, 2 * (int64_t)std::max(cus, 1) / slabs);
+    int64_t rpw = (m + per_slab - 1) / per_slab;
+    rpw = (rpw + 31) / 32 * 32;
+    const int64_t chunks = (m + rpw - 1) / rpw;
+    const size_t lds = (size_t)((p + 15) / 16 * 16) * kTile * sizeof(double);
     hipLaunchKernelGGL(k_upd, dim3((unsigned)(chunks * slabs)), dim3(256), lds, s, m, p, q, L, ldl,
                        Y, ldy, Cin, ldci, C, ldc, slabs, rpw, info);
     return hipGetLastError();

@@ -288,7 +288,7 @@ def main():
                           "bytes_per_launch": p["bytes"] / p["launches"]}
     log("per-kernel: " + json.dumps({k: {kk: round(vv, 3) for kk, vv in v.items()}
                                       for k, v in kern.items()}))
-    dom = max((k for k in kern if k in ("gram", "proj", "update", "trsm")),
+    dom = max((k for k in kern if k in ("gram", "proj", "update", "update_long", "trsm")),
               key=lambda k: kern[k]["ms_per_step"])
     kd = kern[dom]
     intensity = kd["flops_per_launch"] / kd["bytes_per_launch"]

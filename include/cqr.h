@@ -179,14 +179,15 @@ const char *cqr_status_string(int status);
 enum cqr_kernel_kind {
   CQR_K_GRAM = 0,     /* split-m Gram partials of a panel (SYRK) */
   CQR_K_PROJ = 1,     /* split-m projection partials Y = Q_j^T Z */
-  CQR_K_UPDATE = 2,   /* trailing update Z -= Q_j Y */
+  CQR_K_UPDATE = 2,   /* trailing update Z -= Q_j Y, inner dimension <= 128 */
   CQR_K_TRSM = 3,     /* Q_j = X U^{-1} (explicit inverse, streaming GEMM) */
   CQR_K_REDUCE = 4,   /* fixed-order sum of split-m partials */
   CQR_K_CHOL = 5,     /* b x b Cholesky + triangular inverse, one workgroup */
   CQR_K_SMALL = 6,    /* small R-block products and fills */
   CQR_K_BATCHED = 7,  /* the persistent batched factorisation (whole launch) */
-  CQR_K_COPY = 8,     /* copies into and out of the staging buffer */
-  CQR_K_COUNT = 9
+  CQR_K_COPY = 8,     /* copy into the staging buffer */
+  CQR_K_UPDATE_LONG = 9, /* update Qt -= Q_{1:j-1} Z, inner dimension > 128 */
+  CQR_K_COUNT = 10
 };
 int cqr_profile_enable(int on);
 int cqr_profile_reset(void);

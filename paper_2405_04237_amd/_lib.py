@@ -23,7 +23,8 @@ SCHED_MOD = 0
 SCHED_ORIG = 1
 SCHEDULES = {"mod": SCHED_MOD, "orig": SCHED_ORIG}
 
-KERNEL_KINDS = ["gram", "proj", "update", "trsm", "reduce", "chol", "small", "batched", "copy"]
+KERNEL_KINDS = ["gram", "proj", "update", "trsm", "reduce", "chol", "small", "batched", "copy",
+                "update_long"]
 
 # Every symbol include/cqr.h declares, with its ctypes signature.
 _I64, _VP, _DP = C.c_int64, C.c_void_p, C.c_void_p

@@ -216,7 +216,8 @@ hipError_t step_proj(Run &r, const double *Qp, int64_t ld, int p, const double *
 // Zo = Zi - Qp Y  (r.Y holds -Y); Zo may be Zi (in place)
 hipError_t step_update(Run &r, const double *Qp, int64_t ld, int p, const double *Zi, double *Zo,
                        int q) {
-  return timed(r.s, CQR_K_UPDATE, 2.0 * r.m * p * q, 8.0 * r.m * (p + 2.0 * q), [&] {
+  const int kind = cqr::nn_short_k(p, Qp, ld, Zi, ld, Zo, ld) ? CQR_K_UPDATE : CQR_K_UPDATE_LONG;
+  return timed(r.s, kind, 2.0 * r.m * p * q, 8.0 * r.m * (p + 2.0 * q), [&] {
     return cqr::launch_nn(true, false, r.m, p, q, Qp, ld, r.Y, cqr::padded_ld(q), Zi, ld, Zo, ld,
                           r.info, r.s);
   });

@@ -47,6 +47,11 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
                      int64_t sL = 0, int64_t sL2 = 0, int64_t sY = 0, int64_t sCin = 0,
                      int64_t sC = 0, double *C2 = nullptr, int64_t ldc2 = 0);
 
+// True when launch_nn runs a single-matrix subtract = true product through
+// the short-inner-dimension kernel (Y staged in LDS); false: the general one.
+bool nn_short_k(int p, const double *L, int64_t ldl, const double *Cin, int64_t ldci,
+                const double *C, int64_t ldc);
+
 // Leading dimension used for row-major p x q operands written by the
 // library (a multiple of 4 doubles, so rows stay 32-byte aligned).
 __host__ __device__ inline int64_t padded_ld(int64_t q) { return (q + 3) / 4 * 4; }

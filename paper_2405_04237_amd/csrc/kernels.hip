@@ -407,6 +407,12 @@ __global__ __launch_bounds__(256, (RB == 2) ? 2 : 1) void k_nn(
 // ----------------------------------------------------------------------------
 constexpr int kUpdMaxK = 128;
 
+bool nn_short_k(int p, const double *L, int64_t ldl, const double *Cin, int64_t ldci,
+                const double *C, int64_t ldc) {
+  return p <= kUpdMaxK && (ldl % 2 == 0) && (ldc % 2 == 0) && (ldci % 2 == 0) &&
+         ((uintptr_t)L % 16 == 0) && ((uintptr_t)C % 16 == 0) && ((uintptr_t)Cin % 16 == 0);
+}
+
 __global__ __launch_bounds__(256, 2) void k_upd(int64_t m, int p, int q, const double *L,
                                                 int64_t ldl, const double *__restrict__ Y,
                                                 int64_t ldy, const double *Cin, int64_t ldci,
@@ -724,9 +730,7 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
     return launch_nn(false, true, m - mfull, p, q, L + mfull, ldl, Y, ldy, nullptr, 0, C + mfull,
                      ldc, info, s, nullptr, 0, 0, 1, 0, 0, 0, 0, 0, C2 ? C2 + mfull : nullptr, ldc2);
   }
-  if (subtract && batch == 1 && psplit == p && p <= kUpdMaxK && (ldl % 2 == 0) &&
-      (ldc % 2 == 0) && (ldci % 2 == 0) && ((uintptr_t)L % 16 == 0) &&
-      ((uintptr_t)C % 16 == 0) && ((uintptr_t)Cin % 16 == 0)) {
+  if (subtract && batch == 1 && psplit == p && nn_short_k(p, L, ldl, Cin, ldci, C, ldc)) {
     // one round of resident workgroups (two per CU): each slab gets an equal
     // share of them, each with an equal range of rows (a multiple of 32)
     static bool attr = false;

@@ -23,11 +23,10 @@ namespace cqr {
 namespace {
 
 constexpr int kThreads = 256;
-// Row sums are accumulated on three levels so that no running sum takes more
-// than a few hundred sequential additions: MFMA accumulators over kInnerRows
-// rows, a second register set over kFlushRows rows, then the LDS result.
-constexpr int kInnerRows = 512;
-constexpr int kFlushRows = 4096;
+// A wave's MFMA accumulators cover at most kTnFlushRows of its rows before
+// they are added into the LDS result (the four waves in a fixed order), so
+// no running sum sees more than ~128 sequential additions at either level.
+constexpr int kTnFlushRows = 512;
 
 // LDS layout (doubles)
 constexpr int kYSize = kBatchMaxPanel * kBatchMaxN + 64;  // projections (+ read slack)
@@ -58,183 +57,281 @@ __device__ inline void wg_sync() {
   __threadfence();
 }
 
-// out (LDS, row-major, ld ldo) = L^T Rt over rows [0, m); L is m x p, Rt m x q
-// (column-major). upper: only 16x16 blocks on or above the diagonal. Each wave
-// owns up to 4 output blocks and sweeps all rows, flushing its accumulators
-// into `out` every kFlushRows rows (a fixed order). The caller guarantees at
-// most 16 blocks (b <= 32 and n <= 128 give at most 2 x 8).
-__device__ __forceinline__ void wg_tn(int64_t m, int p, int q, const double *L, int64_t ldl, const double *Rt,
-                      int64_t ldr, bool upper, double *out, int ldo) {
+// ---------------------------------------------------------------------------
+// TN product reduced over the rows: out (LDS) = A^T B over rows [0, m), A is
+// m x na and B m x nb (column-major; na <= 16 NA, nb <= 16 NB columns). The
+// four waves split the rows (wave w takes the w-th SR-row block of every
+// 4 SR-row round) and each accumulates every 16 x 16 output block, so each
+// column line is loaded once per wave; loads run through a three-deep
+// register ring. trans = false: out[i * ldo + j]; true: out[j * ldo + i].
+// Lane maps as in the single-matrix k_tn: lane (cl, g) feeds rows 4g..4g+3
+// of column 16 a + cl; D element e of block (a, b) is (16a + g + 4e, 16b + cl).
+// ---------------------------------------------------------------------------
+template <int NA, int NB>
+__device__ __forceinline__ void tn_run(int64_t m, int na, int nb, const double *A, int64_t lda,
+                                       const double *B, int64_t ldb, bool vec, double *out, int ldo,
+                                       bool trans) {
+  constexpr int U = (NA + NB <= 2) ? 4 : ((NA + NB) * 2 <= 10 ? 2 : 1);  // 16-row steps per stage
+  constexpr int SR = 16 * U;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, cl = lane & 15;
-  for (int e = tid; e < p * ldo; e += kThreads) out[e] = 0.0;
+  const int rows_out = trans ? nb : na;
+  for (int e = tid; e < rows_out * ldo; e += kThreads) out[e] = 0.0;
   __syncthreads();
-  const int nbp = (p + 15) / 16, nbq = (q + 15) / 16;
-  const int total = upper ? nbp * (nbp + 1) / 2 : nbp * nbq;
-  // block t of this wave is number wave + 4 t of the list (row-major over
-  // (i, j), j >= i when upper); decoded without indexing registers dynamically
-  int bi[4], bj[4];
-  bool own[4];
+
+  // columns past na / nb read column 0: they reach only outputs never stored
+  const double *pa[NA];
+  const double *pb[NB];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    int lin = wave + 4 * t;
-    own[t] = lin < total;
-    int i = 0, j = 0;
-    if (own[t]) {
-      if (upper) {
-        int len = nbp;
-        while (lin >= len) {
-          lin -= len;
-          ++i;
-          --len;
-        }
-        j = i + lin;
-      } else {
-        i = lin / nbq;
-        j = lin % nbq;
-      }
-    }
-    bi[t] = i;
-    bj[t] = j;
+  for (int a = 0; a < NA; ++a) {
+    const int c = 16 * a + cl;
+    pa[a] = A + (int64_t)(c < na ? c : 0) * lda + 4 * g + wave * SR;
   }
-  const int nb = own[3] ? 4 : own[2] ? 3 : own[1] ? 2 : own[0] ? 1 : 0;
-  if (nb > 0) {
-    const double *pa[4];
-    const double *pb[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int ca = 16 * bi[t] + cl, cb = 16 * bj[t] + cl;
-      pa[t] = L + (int64_t)(ca < p ? ca : 0) * ldl + 4 * g;
-      pb[t] = Rt + (int64_t)(cb < q ? cb : 0) * ldr + 4 * g;
-    }
-    d4 acc[4], acc2[4];
-    auto fold = [&]() {  // acc2 += acc; acc = 0
+  for (int b = 0; b < NB; ++b) {
+    const int c = 16 * b + cl;
+    pb[b] = B + (int64_t)(c < nb ? c : 0) * ldb + 4 * g + wave * SR;
+  }
+  d4 acc[NA][NB];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+  for (int a = 0; a < NA; ++a)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc2[t][e] += acc[t][e];
-        acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-      }
-    };
-    auto flush = [&]() {  // out += acc2; acc2 = 0
+    for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+  auto flush = [&]() {  // out += acc, wave 0 first; acc = 0
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (t < nb) {
+    for (int w = 0; w < 4; ++w) {
+      if (wave == w) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int I = 16 * bi[t] + g + 4 * e, J = 16 * bj[t] + cl;
-            if (I < p && J < q) out[I * ldo + J] += acc2[t][e];
-          }
-        }
-        acc2[t] = d4{0.0, 0.0, 0.0, 0.0};
-      }
-    };
+        for (int a = 0; a < NA; ++a)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-      acc2[t] = d4{0.0, 0.0, 0.0, 0.0};
-    }
-    const int64_t full = m / 16 * 16;
-    double a[4][4], b[4][4];
-    for (int64_t r0 = 0; r0 < full; r0 += kFlushRows) {
-      const int64_t r1 = (r0 + kFlushRows < full) ? r0 + kFlushRows : full;
-      for (int64_t ri = r0; ri < r1; ri += kInnerRows) {
-        const int64_t r2 = (ri + kInnerRows < r1) ? ri + kInnerRows : r1;
-        for (int64_t r = ri; r < r2; r += 16) {
+          for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-              a[t][s] = pa[t][r + s];
-              b[t][s] = pb[t][r + s];
+            for (int e = 0; e < 4; ++e) {
+              const int I = 16 * a + g + 4 * e, J = 16 * b + cl;
+              if (I < na && J < nb) out[trans ? J * ldo + I : I * ldo + J] += acc[a][b][e];
             }
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-              if (t < nb) acc[t] = mfma16x16x4(a[t][s], b[t][s], acc[t]);
-        }
-        fold();
       }
-      flush();
+      __syncthreads();
     }
-    if (full < m) {  // ragged tail
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+    for (int a = 0; a < NA; ++a)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const bool ok = full + 4 * g + s < m;
-          a[t][s] = ok ? pa[t][full + s] : 0.0;
-          b[t][s] = ok ? pb[t][full + s] : 0.0;
+      for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  };
+  typedef double Stage[NA + NB][U][4];
+  auto load = [&](Stage &v, int64_t off) {  // off: row offset of the round
+#pragma unroll
+    for (int c = 0; c < NA + NB; ++c) {
+      const double *p = (c < NA ? pa[c] : pb[c - NA]) + off;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (vec) {
+          const double2 x0 = reinterpret_cast<const double2 *>(p + 16 * u)[0];
+          const double2 x1 = reinterpret_cast<const double2 *>(p + 16 * u)[1];
+          v[c][u][0] = x0.x;
+          v[c][u][1] = x0.y;
+          v[c][u][2] = x1.x;
+          v[c][u][3] = x1.y;
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) v[c][u][s] = p[16 * u + s];
         }
+      }
+    }
+  };
+  auto compute = [&](const Stage &v) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-          if (t < nb) acc[t] = mfma16x16x4(a[t][s], b[t][s], acc[t]);
-      fold();
-      flush();
+        for (int a = 0; a < NA; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+            acc[a][b] = mfma16x16x4(v[a][u][s], v[NA + b][u][s], acc[a][b]);
+  };
+
+  const int64_t round_rows = 4 * SR;
+  const int64_t nfull = m / round_rows;               // rounds with every row present
+  const int64_t per_flush = kTnFlushRows / SR;        // rounds between flushes
+  if (nfull > 0) {
+    auto at = [&](int64_t r) -> int64_t { return round_rows * (r < nfull ? r : nfull - 1); };
+    auto step = [&](const Stage &v, int64_t r) {
+      compute(v);
+      if ((r + 1) % per_flush == 0) flush();
+    };
+    if constexpr (NA + NB > 6) {  // wide products: two stages (64 MFMAs of cover each)
+      Stage v0, v1;
+      load(v0, 0);
+      int64_t r = 0;
+      for (; r + 2 <= nfull; r += 2) {
+        load(v1, at(r + 1));
+        __builtin_amdgcn_sched_barrier(0);
+        step(v0, r);
+        __builtin_amdgcn_sched_barrier(0);
+        load(v0, at(r + 2));
+        __builtin_amdgcn_sched_barrier(0);
+        step(v1, r + 1);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (r < nfull) step(v0, r);
+    } else {
+      Stage v0, v1, v2;
+      load(v0, 0);
+      load(v1, at(1));
+      int64_t r = 0;
+      for (; r + 3 <= nfull; r += 3) {
+        load(v2, at(r + 2));
+        __builtin_amdgcn_sched_barrier(0);
+        step(v0, r);
+        __builtin_amdgcn_sched_barrier(0);
+        load(v0, at(r + 3));
+        __builtin_amdgcn_sched_barrier(0);
+        step(v1, r + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        load(v1, at(r + 4));
+        __builtin_amdgcn_sched_barrier(0);
+        step(v2, r + 2);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (r < nfull) step(v0, r);
+      if (r + 1 < nfull) step(v1, r + 1);
     }
   }
+  // the last, partial round: rows past m contribute zeros
+  const int64_t rt = nfull * round_rows;
+  if (rt < m) {
+    Stage v;
+#pragma unroll
+    for (int c = 0; c < NA + NB; ++c) {
+      const double *p = (c < NA ? pa[c] : pb[c - NA]) + rt;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int64_t row = rt + wave * SR + 16 * u + 4 * g + s;
+          v[c][u][s] = (row < m) ? p[16 * u + s] : 0.0;
+        }
+    }
+    compute(v);
+  }
+  flush();
   wg_sync();
 }
 
-// C = L Y (+ Cin when sub) over rows [0, m): L m x p column-major, Y p x q
-// row-major in LDS (ld ldy, padded so that 4-wide reads past q stay in the Y
-// region), Cin / C m x q column-major. C may alias L only when each wave's
-// tile covers all of C's columns (q <= 64): a wave reads its rows of L fully
-// before it writes them. 64 x 64 tiles are dealt to the waves round-robin.
-__device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, int64_t ldl, const double *Y, int ldy,
-                      const double *Cin, int64_t ldci, double *C, int64_t ldc, bool sub) {
+// One call site for every TN product of the factorisation: dispatch on the
+// block counts (A side <= 2 blocks: the panel; B side <= 8: up to 128 columns).
+__device__ __forceinline__ void wg_tn(int64_t m, int na, int nb, const double *A, int64_t lda,
+                                   const double *B, int64_t ldb, double *out, int ldo, bool trans) {
+  const bool vec = (lda % 2 == 0) && (ldb % 2 == 0) && ((uintptr_t)A % 16 == 0) &&
+                   ((uintptr_t)B % 16 == 0);
+  const int ka = (na + 15) / 16, kb = (nb + 15) / 16;
+#define CQR_TN_CASE(X, Y)                                             \
+  if (ka == X && kb == Y) {                                           \
+    tn_run<X, Y>(m, na, nb, A, lda, B, ldb, vec, out, ldo, trans);    \
+    return;                                                           \
+  }
+  CQR_TN_CASE(1, 1) CQR_TN_CASE(1, 2) CQR_TN_CASE(1, 3) CQR_TN_CASE(1, 4)
+  CQR_TN_CASE(1, 5) CQR_TN_CASE(1, 6) CQR_TN_CASE(1, 7) CQR_TN_CASE(1, 8)
+  CQR_TN_CASE(2, 1) CQR_TN_CASE(2, 2) CQR_TN_CASE(2, 3) CQR_TN_CASE(2, 4)
+  CQR_TN_CASE(2, 5) CQR_TN_CASE(2, 6) CQR_TN_CASE(2, 7) CQR_TN_CASE(2, 8)
+#undef CQR_TN_CASE
+}
+
+// ---------------------------------------------------------------------------
+// Row-streaming NN product C = L Y (+ Cin when sub) over rows [0, m): L m x p
+// column-major, Y p x q row-major in LDS (ld ldy; reads up to 64 columns past
+// a tile's start stay inside the LDS region), Cin / C m x q column-major.
+// 32 x 64 tiles are dealt to the waves round-robin (tile t: row tile t / nct,
+// column tile t % nct). The k steps of a wave's consecutive full tiles form
+// one stream through a three-deep register ring; a tile's first stage also
+// carries its Cin. C may alias L when q <= 64 (a wave reads its tile's rows
+// fully before writing them, and no other wave touches those rows); Cin may
+// equal C. Lane maps as in k_nn with two rows per lane.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, int64_t ldl,
+                                   const double *Y, int ldy, const double *Cin, int64_t ldci,
+                                   double *C, int64_t ldc, bool sub) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, cl = lane & 15;
-  const int64_t nrt = (m + 63) / 64;
+  const bool vec = (ldl % 2 == 0) && (ldc % 2 == 0) && (!sub || ldci % 2 == 0) &&
+                   ((uintptr_t)L % 16 == 0) && ((uintptr_t)C % 16 == 0) &&
+                   (!sub || (uintptr_t)Cin % 16 == 0);
   const int nct = (q + 63) / 64;
-  for (int64_t t = wave; t < nrt * nct; t += 4) {
-    const int64_t r0 = (t / nct) * 64;
-    const int c0 = (int)(t % nct) * 64;
-    const int64_t rl = r0 + 4 * cl;
-    const bool full_rows = r0 + 64 <= m;
-    d4 acc[4][4];
+  const int nk = (p + 15) / 16;
+  const int64_t nrt_full = m / 32;
+  const int64_t nt_full = nrt_full * nct;
+  const int64_t mine = (nt_full > wave) ? (nt_full - wave + 3) / 4 : 0;  // full tiles of this wave
+  const int64_t T = mine * nk;                                            // steps
+
+  struct Stage {
+    double l[4][2];     // L[rl + y][k], k = 16 ks + 4 s + g
+    double c[4][4][2];  // Cin[rl + y][c0 + 4 g + 16 e + x] (a tile's first step)
+  };
+  d4 acc[4][2];
+
+  auto tile_of = [&](int64_t i, int64_t &r0, int &c0) {  // i-th tile of this wave
+    const int64_t t = wave + 4 * i;
+    r0 = (t / nct) * 32;
+    c0 = (int)(t % nct) * 64;
+  };
+  auto load_l = [&](double (&l)[4][2], int64_t rl, int ks, int64_t rows_left) {
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int s = 0; s < 4; ++s) {
+      const int k = 16 * ks + 4 * s + g;
+      const double *pl = L + (int64_t)(k < p ? k : p - 1) * ldl + rl;
+      double x0, x1;
+      if (vec && rows_left >= 2) {
+        const double2 t = *reinterpret_cast<const double2 *>(pl);
+        x0 = t.x;
+        x1 = t.y;
+      } else {
+        x0 = (rows_left > 0) ? pl[0] : 0.0;
+        x1 = (rows_left > 1) ? pl[1] : 0.0;
+      }
+      l[s][0] = (k < p) ? x0 : 0.0;
+      l[s][1] = (k < p) ? x1 : 0.0;
+    }
+  };
+  auto load_c = [&](double (&cv)[4][4][2], int64_t rl, int c0, int64_t rows_left) {
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
-    if (sub) {
+    for (int e = 0; e < 4; ++e)
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          const int col = c0 + 4 * g + 16 * e + x;
-          if (col < q) {
-            const double *pc = Cin + (int64_t)col * ldci + rl;
-#pragma unroll
-            for (int y = 0; y < 4; ++y) acc[x][y][e] = (rl + y < m) ? pc[y] : 0.0;
+      for (int x = 0; x < 4; ++x) {
+        const int col = c0 + 4 * g + 16 * e + x;
+        double x0 = 0.0, x1 = 0.0;
+        if (sub && col < q) {
+          const double *pc = Cin + (int64_t)col * ldci + rl;
+          if (vec && rows_left >= 2) {
+            const double2 t = *reinterpret_cast<const double2 *>(pc);
+            x0 = t.x;
+            x1 = t.y;
+          } else {
+            x0 = (rows_left > 0) ? pc[0] : 0.0;
+            x1 = (rows_left > 1) ? pc[1] : 0.0;
           }
         }
-    }
-    const double *yb = Y + c0 + 4 * cl;
-    const double *lb = L + (full_rows ? rl : 0);
-    for (int kk = 0; kk < p; kk += 4) {
-      const int k = kk + g;
-      const bool kok = k < p;
-      const int ks = kok ? k : 0;
-      double av[4], bv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double yv = yb[ks * ldy + u];
-        av[u] = kok ? yv : 0.0;
+        cv[e][x][0] = x0;
+        cv[e][x][1] = x1;
       }
-      if (full_rows) {
+  };
+  auto mma = [&](const double (&l)[4][2], int ks, int c0) {
+    const double *yl = Y + c0 + 4 * cl;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) bv[u] = kok ? lb[(int64_t)ks * ldl + u] : 0.0;
-      } else {
+    for (int s = 0; s < 4; ++s) {
+      const int k = 16 * ks + 4 * s + g;
+      double ya[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) bv[u] = (kok && rl + u < m) ? L[(int64_t)ks * ldl + rl + u] : 0.0;
+      for (int x = 0; x < 4; ++x) {
+        const double yv = yl[(k < p ? k : 0) * ldy + x];
+        ya[x] = (k < p) ? yv : 0.0;
       }
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x4(av[x], bv[y], acc[x][y]);
+        for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x4(ya[x], l[s][y], acc[x][y]);
     }
+  };
+  auto store = [&](int64_t rl, int c0, int64_t rows_left) {
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
@@ -242,11 +339,94 @@ __device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, 
         const int col = c0 + 4 * g + 16 * e + x;
         if (col < q) {
           double *pc = C + (int64_t)col * ldc + rl;
-#pragma unroll
-          for (int y = 0; y < 4; ++y)
-            if (rl + y < m) pc[y] = acc[x][y][e];
+          if (vec && rows_left >= 2) {
+            *reinterpret_cast<double2 *>(pc) = double2{acc[x][0][e], acc[x][1][e]};
+          } else {
+            if (rows_left > 0) pc[0] = acc[x][0][e];
+            if (rows_left > 1) pc[1] = acc[x][1][e];
+          }
         }
       }
+  };
+  auto init_acc = [&](const double (&cv)[4][4][2]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        acc[x][0][e] = cv[e][x][0];
+        acc[x][1][e] = cv[e][x][1];
+      }
+  };
+
+  if (T > 0) {
+    // load cursor
+    int64_t li = 0, lr0;
+    int lc0, lks = 0;
+    tile_of(0, lr0, lc0);
+    int64_t lt = 0;
+    auto load = [&](Stage &st) {
+      const int64_t rl = lr0 + 2 * cl;
+      load_l(st.l, rl, lks, 2);
+      if (lks == 0) load_c(st.c, rl, lc0, 2);
+      if (lt + 1 < T) {  // advance (past the end the last step is loaded again)
+        ++lt;
+        if (++lks == nk) {
+          lks = 0;
+          tile_of(++li, lr0, lc0);
+        }
+      }
+    };
+    // compute cursor
+    int64_t ci = 0, cr0;
+    int cc0, cks = 0;
+    tile_of(0, cr0, cc0);
+    auto step = [&](const Stage &st) {
+      if (cks == 0) init_acc(st.c);
+      mma(st.l, cks, cc0);
+      if (++cks == nk) {
+        store(cr0 + 2 * cl, cc0, 2);
+        cks = 0;
+        tile_of(++ci, cr0, cc0);
+      }
+    };
+    Stage s0, s1, s2;
+    load(s0);
+    load(s1);
+    int64_t t = 0;
+    for (; t + 3 <= T; t += 3) {
+      load(s2);
+      __builtin_amdgcn_sched_barrier(0);
+      step(s0);
+      __builtin_amdgcn_sched_barrier(0);
+      load(s0);
+      __builtin_amdgcn_sched_barrier(0);
+      step(s1);
+      __builtin_amdgcn_sched_barrier(0);
+      load(s1);
+      __builtin_amdgcn_sched_barrier(0);
+      step(s2);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (t < T) step(s0);
+    if (t + 1 < T) step(s1);
+  }
+  // the last, partial row tile (fewer than 32 rows), masked
+  if (nrt_full * 32 < m) {
+    for (int ct = 0; ct < nct; ++ct) {
+      if ((int)((nt_full + ct) % 4) != wave) continue;
+      const int64_t r0 = nrt_full * 32;
+      const int c0 = ct * 64;
+      const int64_t rl = r0 + 2 * cl;
+      const int64_t left = m - rl;
+      Stage st;
+      load_c(st.c, rl, c0, left);
+      init_acc(st.c);
+      for (int ks = 0; ks < nk; ++ks) {
+        load_l(st.l, rl, ks, left);
+        mma(st.l, ks, c0);
+      }
+      store(rl, c0, left);
+    }
   }
   wg_sync();
 }
@@ -293,66 +473,103 @@ __device__ __forceinline__ void wg_r_upper_product(double *R, int n, int r0, int
   }
 }
 
-// mCQR2GS of one matrix by one workgroup. Returns 0 or the breakdown column.
-__device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int64_t m, int n, int b, const double *A, int64_t lda,
-                          double *Q, double *R) {
+// mCQR2GS of one matrix by one workgroup, as a sequence of phases with one
+// call site per streaming primitive. Returns 0 or the breakdown column.
+__device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int64_t m, int n, int b, const double *A,
+                                          int64_t lda, double *Q, double *R) {
   const int tid = threadIdx.x;
   for (int e = tid; e < n * n; e += kThreads) R[e] = 0.0;
   const int w0 = n < b ? n : b;
-  int ldu = (int)padded_ld(w0);
-  // first panel: CholeskyQR2, reading A and writing Q
-  wg_tn(m, w0, w0, A, lda, A, lda, true, S.w, w0);
-  int fail = wg_chol_inv(S, w0, S.ua, ldu);
-  if (fail) return fail;
-  wg_nn(m, w0, w0, A, lda, S.ui, ldu, nullptr, 0, Q, lda, false);
-  wg_tn(m, w0, w0, Q, lda, Q, lda, true, S.w, w0);
-  fail = wg_chol_inv(S, w0, S.ub, ldu);
-  if (fail) return fail;
-  wg_nn(m, w0, w0, Q, lda, S.ui, ldu, nullptr, 0, Q, lda, false);
-  wg_r_upper_product(R, n, 0, w0, S.ub, S.ua);
-  for (int s = b; s < n; s += b) {
-    const int ps = s - b, w = (n - s < b) ? n - s : b, nr = n - s;
-    const double *Ar = (ps == 0) ? A + (int64_t)s * lda : Q + (int64_t)s * lda;
+  int s = 0;  // first column of the current panel
+  int w = w0;
+  int ph = 0;
+  for (;;) {
+    // one of: TN product, NN product, or a small step done in place
+    int op = 0;  // 1 = TN, 2 = NN
+    int64_t tm = m;
+    int ta = 0, tb = 0, tldo = 0, np = 0, nq = 0, nldy = 0;
+    const double *tA = nullptr, *tB = nullptr, *nL = nullptr, *nY = nullptr, *nCin = nullptr;
+    double *tout = nullptr, *nC = nullptr;
+    bool ttrans = false, nsub = false;
+    const int ps = s - b, nr = n - s;
     double *Xj = Q + (int64_t)s * lda;
-    const double *Qprev = Q + (int64_t)ps * lda;
-    // Y := Q_{j-1}^T A_{:,j:k}; R_{j-1,j:k} := Y; A_{:,j:k} -= Q_{j-1} Y
-    int ldy = (int)padded_ld(nr);
-    wg_tn(m, b, nr, Qprev, lda, Ar, lda, false, S.y, ldy);
-    for (int e = tid; e < b * nr; e += kThreads) {
-      const int i = e / nr, j = e % nr;
-      R[(ps + i) + (int64_t)(s + j) * n] = S.y[i * ldy + j];
-      S.y[i * ldy + j] = -S.y[i * ldy + j];
+    const int ldw = (int)padded_ld(w);
+    bool next = false;
+    switch (ph) {
+      // first panel: CholeskyQR2, reading A and writing Q
+      case 0: op = 1; ta = tb = w; tA = tB = A; tout = S.w; tldo = w; break;
+      case 1: { const int f = wg_chol_inv(S, w, S.ua, ldw); if (f) return f; break; }
+      case 2: op = 2; np = nq = w; nL = A; nY = S.ui; nldy = ldw; nC = Q; break;
+      case 3: op = 1; ta = tb = w; tA = tB = Q; tout = S.w; tldo = w; break;
+      case 4: { const int f = wg_chol_inv(S, w, S.ub, ldw); if (f) return f; break; }
+      case 5: op = 2; np = nq = w; nL = Q; nY = S.ui; nldy = ldw; nC = Q; break;
+      case 6:
+        wg_r_upper_product(R, n, 0, w, S.ub, S.ua);
+        next = true;
+        break;
+      // panel s >= b: Y := Q_{j-1}^T A_{:,j:k}; R_{j-1,j:k} := Y; A_{:,j:k} -= Q_{j-1} Y
+      case 7:
+        op = 1; ta = b; tb = nr; tA = Q + (int64_t)ps * lda; tB = (ps == 0) ? A + (int64_t)s * lda : Xj;
+        tout = S.y; tldo = (int)padded_ld(nr);
+        break;
+      case 8: {
+        const int ldy = (int)padded_ld(nr);
+        for (int e = tid; e < b * nr; e += kThreads) {
+          const int i = e / nr, j = e % nr;
+          R[(ps + i) + (int64_t)(s + j) * n] = S.y[i * ldy + j];
+          S.y[i * ldy + j] = -S.y[i * ldy + j];
+        }
+        __syncthreads();
+        break;
+      }
+      case 9:
+        op = 2; np = b; nq = nr; nL = Q + (int64_t)ps * lda; nY = S.y; nldy = (int)padded_ld(nr);
+        nCin = (ps == 0) ? A + (int64_t)s * lda : Xj; nC = Xj; nsub = true;
+        break;
+      // CQR of panel j: A_j = Qt Ua
+      case 10: op = 1; ta = tb = w; tA = tB = Xj; tout = S.w; tldo = w; break;
+      case 11: { const int f = wg_chol_inv(S, w, S.ua, ldw); if (f) return s + f; break; }
+      case 12: op = 2; np = nq = w; nL = Xj; nY = S.ui; nldy = ldw; nC = Xj; break;
+      // re-orthogonalise: Z := Q_{1:j-1}^T Qt (computed as Qt^T Q_{1:j-1}, stored transposed)
+      case 13: op = 1; ta = w; tb = s; tA = Xj; tB = Q; tout = S.y; tldo = ldw; ttrans = true; break;
+      case 14: {
+        // R_{1:j-1,j} += Z Ua; then Y := -Z for the update
+        for (int e = tid; e < s * w; e += kThreads) {
+          const int i = e % s, c = e / s;
+          double acc = 0.0;
+          for (int k = 0; k <= c; ++k) acc += S.y[i * ldw + k] * S.ua[k * w + c];
+          R[i + (int64_t)(s + c) * n] += acc;
+        }
+        __syncthreads();
+        for (int e = tid; e < s * ldw; e += kThreads) S.y[e] = -S.y[e];
+        __syncthreads();
+        break;
+      }
+      case 15: op = 2; np = s; nq = w; nL = Q; nY = S.y; nldy = ldw; nCin = Xj; nC = Xj; nsub = true; break;
+      // CQR again: Qt = Q_j Ub; R_jj = Ub Ua
+      case 16: op = 1; ta = tb = w; tA = tB = Xj; tout = S.w; tldo = w; break;
+      case 17: { const int f = wg_chol_inv(S, w, S.ub, ldw); if (f) return s + f; break; }
+      case 18: op = 2; np = nq = w; nL = Xj; nY = S.ui; nldy = ldw; nC = Xj; break;
+      case 19:
+        wg_r_upper_product(R, n, s, w, S.ub, S.ua);
+        __syncthreads();
+        next = true;
+        break;
     }
-    __syncthreads();
-    wg_nn(m, b, nr, Qprev, lda, S.y, ldy, Ar, lda, Xj, lda, true);
-    // CQR of panel j: A_j = Qt Ua
-    ldu = (int)padded_ld(w);
-    wg_tn(m, w, w, Xj, lda, Xj, lda, true, S.w, w);
-    fail = wg_chol_inv(S, w, S.ua, ldu);
-    if (fail) return s + fail;
-    wg_nn(m, w, w, Xj, lda, S.ui, ldu, nullptr, 0, Xj, lda, false);
-    // re-orthogonalise: Z := Q_{1:j-1}^T Qt; Qt -= Q_{1:j-1} Z; R_{1:j-1,j} += Z Ua
-    ldy = (int)padded_ld(w);
-    wg_tn(m, s, w, Q, lda, Xj, lda, false, S.y, ldy);
-    for (int e = tid; e < s * w; e += kThreads) {
-      const int i = e % s, c = e / s;
-      double acc = 0.0;
-      for (int k = 0; k <= c; ++k) acc += S.y[i * ldy + k] * S.ua[k * w + c];
-      R[i + (int64_t)(s + c) * n] += acc;
+    if (op == 1) {
+      wg_tn(tm, ta, tb, tA, lda, tB, lda, tout, tldo, ttrans);
+    } else if (op == 2) {
+      wg_nn(tm, np, nq, nL, lda, nY, nldy, nCin ? nCin : nC, lda, nC, lda, nsub);
     }
-    __syncthreads();
-    for (int e = tid; e < s * ldy; e += kThreads) S.y[e] = -S.y[e];
-    __syncthreads();
-    wg_nn(m, s, w, Q, lda, S.y, ldy, Xj, lda, Xj, lda, true);
-    // CQR again: Qt = Q_j Ub; R_jj = Ub Ua
-    wg_tn(m, w, w, Xj, lda, Xj, lda, true, S.w, w);
-    fail = wg_chol_inv(S, w, S.ub, ldu);
-    if (fail) return s + fail;
-    wg_nn(m, w, w, Xj, lda, S.ui, ldu, nullptr, 0, Xj, lda, false);
-    wg_r_upper_product(R, n, s, w, S.ub, S.ua);
-    __syncthreads();
+    if (next) {
+      if (s == 0) s = b; else s += b;
+      if (s >= n) return 0;
+      w = (n - s < b) ? n - s : b;
+      ph = 7;
+    } else {
+      ++ph;
+    }
   }
-  return 0;
 }
 
 __global__ void k_set_int_batched(int *p) { *p = 0; }

@@ -29,6 +29,22 @@ constexpr int64_t kPartChunks = 256;   // split-m partial capacity, in units of 
 constexpr int64_t kTargetWaves = 2048; // split-m grid size aimed for (8 waves per CU)
 constexpr int64_t kMaxChunkRows = 16384;
 
+// Waves of the split-m product kernel resident at once on MI355X (256 CUs x 4
+// SIMDs, one wave each). Grids are sized to whole multiples of it so that no
+// round of waves runs nearly empty; a constant, so the plan (and with it the
+// rounding of every sum) does not depend on the device queried.
+constexpr int64_t kWaveSlots = 1024;
+
+// Number of row chunks for `units` output tiles (x batch): at least
+// kTargetWaves waves and chunks of at most kMaxChunkRows rows, rounded down
+// to fill whole rounds of kWaveSlots waves.
+int64_t split_m_chunks(int64_t m, int64_t units) {
+  const int64_t min_chunks = (m + kMaxChunkRows - 1) / kMaxChunkRows;
+  const int64_t waves = std::max(kTargetWaves, units * min_chunks);
+  const int64_t rounds = (waves + kWaveSlots - 1) / kWaveSlots;
+  return std::max<int64_t>(1, rounds * kWaveSlots / units);
+}
+
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 // Column strides that are multiples of 8 KiB put the 128 column lines one
@@ -151,8 +167,7 @@ struct Run {
 
 void plan_chunks(const Run &r, int64_t tiles, int64_t pq, int64_t *rc, int64_t *nch) {
   const int64_t cap = std::max<int64_t>(1, r.part_elems / std::max<int64_t>(1, pq));
-  int64_t want = (kTargetWaves + tiles - 1) / tiles;
-  want = std::max(want, (r.m + kMaxChunkRows - 1) / kMaxChunkRows);
+  int64_t want = split_m_chunks(r.m, tiles);
   want = std::min({want, cap, (r.m + 15) / 16, int64_t(4096)});
   want = std::max<int64_t>(want, 1);
   int64_t rows = round_up((r.m + want - 1) / want, 16);
@@ -328,8 +343,7 @@ struct BwdLayout {
 BwdLayout make_bwd_layout(int64_t m, int64_t n, int64_t batch) {
   BwdLayout L{};
   const int64_t tiles = cqr::tn_tiles(true, (int)n, (int)n);
-  int64_t want = (kTargetWaves + tiles * batch - 1) / (tiles * batch);
-  want = std::max(want, (m + kMaxChunkRows - 1) / kMaxChunkRows);
+  int64_t want = split_m_chunks(m, tiles * batch);
   want = std::min({want, (m + 15) / 16, int64_t(1024)});
   want = std::max<int64_t>(want, 1);
   L.rc = round_up((m + want - 1) / want, 16);

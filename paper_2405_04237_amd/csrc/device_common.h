@@ -95,4 +95,174 @@ __device__ inline void lds_upper_inverse(double *S, double *D, int w) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Blocked forms for one workgroup of any size (>= 64 threads) on a matrix of
+// order wp = 16 * 2^k (16 ... 128) held row-major in LDS with stride wp; the
+// caller pads a smaller matrix with the identity. They need a handful of
+// workgroup barriers per 16 columns instead of two per column.
+// ---------------------------------------------------------------------------
+
+// Ordering of LDS accesses among the lanes of one wave.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// W = U^T U in place (upper triangle of S; the strict lower part is left as
+// it was), right-looking by 16-column panels: wave 0 factors the diagonal
+// block, every thread then solves the panel's row block and updates the
+// trailing upper triangle, each element's terms subtracted in column order
+// (the order of the unblocked right-looking algorithm). Returns 0 or the
+// 1-based column of the first pivot that is not > 0 (NaN included), the
+// same in every thread. `flag` is one int of LDS.
+__device__ inline int lds_cholesky_blocked(double *S, int wp, int *flag) {
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+  if (tid == 0) *flag = 0;
+  __syncthreads();
+  for (int p0 = 0; p0 < wp; p0 += 16) {
+    if (tid < 64) {  // diagonal block, one wave
+      for (int k = 0; k < 16; ++k) {
+        const int kk = p0 + k;
+        const double d = S[kk * wp + kk];
+        if (!(d > 0.0)) {
+          if (lane == 0) *flag = kk + 1;
+          break;
+        }
+        const double piv = sqrt(d);
+        wave_lds_sync();
+        if (lane < 16 - k) {
+          const int j = kk + lane;
+          S[kk * wp + j] = (lane == 0) ? piv : S[kk * wp + j] / piv;
+        }
+        wave_lds_sync();
+        // trailing part of the block: rows kk+1.., columns >= row
+        for (int e = lane; e < 16 * 16; e += 64) {
+          const int i = p0 + e / 16, j = p0 + e % 16;
+          if (i > kk && j >= i) S[i * wp + j] -= S[kk * wp + i] * S[kk * wp + j];
+        }
+        wave_lds_sync();
+      }
+    }
+    __syncthreads();
+    const int fail = *flag;
+    if (fail) return fail;
+    const int c0 = p0 + 16, rest = wp - c0;
+    if (rest > 0) {
+      // row block: column j solved by forward substitution through the panel
+      // 16 lanes per column (lane k of the group holds row p0 + k): row k is
+      // final at step k and is broadcast to the rows below it
+      for (int e = tid; e < 16 * rest; e += nt) {
+        const int j = c0 + e / 16, k = e % 16;
+        double v = S[(p0 + k) * wp + j];
+        for (int st = 0; st < 16; ++st) {
+          const double x = __shfl(v / S[(p0 + st) * wp + p0 + st], st, 16);
+          if (k == st) v = x;
+          if (k > st) v -= S[(p0 + st) * wp + p0 + k] * x;
+        }
+        S[(p0 + k) * wp + j] = v;
+      }
+      __syncthreads();
+      // trailing upper triangle
+      for (int e = tid; e < rest * rest; e += nt) {
+        const int i = c0 + e / rest, j = c0 + e % rest;
+        if (j >= i) {
+          double ui[16], uj[16];  // all 32 reads in flight before the products
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            ui[k] = S[(p0 + k) * wp + i];
+            uj[k] = S[(p0 + k) * wp + j];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+          double x = S[i * wp + j];
+#pragma unroll
+          for (int k = 0; k < 16; ++k) x -= ui[k] * uj[k];
+          S[i * wp + j] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  return 0;
+}
+
+// U^{-1} in place of the upper triangle of S (U upper, nonzero diagonal) by
+// block back substitution of U X = I, 16 rows at a time from the bottom:
+// first every thread forms the right-hand sides of block row i from the
+// finished rows below (into tmp, 16 x wp), then one thread per column solves
+// with the 16 x 16 diagonal block (kept transposed in the block's strict
+// lower triangle, its diagonal in dg[16]). Each entry of X is thus a
+// substitution step of U X = I, so U X - I stays at the rounding level of
+// U's entries, which is what Q = A U^{-1} needs. The strict lower triangle
+// of S is overwritten.
+__device__ inline void lds_upper_inverse_blocked(double *S, int wp, double *tmp, double *dg) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int o = wp - 16; o >= 0; o -= 16) {
+    const int ncols = wp - o;
+    for (int e = tid; e < 16 * 16; e += nt) {  // U_ii^T below the diagonal, diagonal to dg
+      const int r = e / 16, t = e % 16;
+      if (t > r) S[(o + t) * wp + o + r] = S[(o + r) * wp + o + t];
+      if (t == r) dg[r] = S[(o + r) * wp + o + r];
+    }
+    for (int e = tid; e < 16 * ncols; e += nt) {
+      const int r = e / ncols, j = o + e % ncols;
+      // four partial sums over k, 16 rows of X at a time (X[k][j] = 0 for k > j)
+      const double *ur = S + (o + r) * wp;
+      double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+      int k0 = o + 16;
+      for (; k0 + 15 <= j; k0 += 16) {
+        double ua[16], xb[16];  // all 32 reads in flight before the products
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          ua[k] = ur[k0 + k];
+          xb[k] = S[(k0 + k) * wp + j];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < 16; k += 4) {
+          x0 += ua[k] * xb[k];
+          x1 += ua[k + 1] * xb[k + 1];
+          x2 += ua[k + 2] * xb[k + 2];
+          x3 += ua[k + 3] * xb[k + 3];
+        }
+      }
+      // the block holding row j: X[k][j] = 0 below the diagonal (k > j)
+      if (k0 <= j) {
+#pragma unroll
+        for (int k = 0; k < 16; k += 4) {
+          if (k0 + k <= j) x0 += ur[k0 + k] * S[(k0 + k) * wp + j];
+          if (k0 + k + 1 <= j) x1 += ur[k0 + k + 1] * S[(k0 + k + 1) * wp + j];
+          if (k0 + k + 2 <= j) x2 += ur[k0 + k + 2] * S[(k0 + k + 2) * wp + j];
+          if (k0 + k + 3 <= j) x3 += ur[k0 + k + 3] * S[(k0 + k + 3) * wp + j];
+        }
+      }
+      tmp[r * wp + j] = ((o + r == j) ? 1.0 : 0.0) - ((x0 + x1) + (x2 + x3));
+    }
+    __syncthreads();
+    // 16 lanes per column (lane r of the group holds row r): x_r is final at
+    // step r, is broadcast within the group, and leaves the rows above
+    for (int e = tid; e < 16 * ncols; e += nt) {
+      const int j = o + e / 16, r = e % 16;
+      double v = tmp[r * wp + j];
+      for (int st = 15; st >= 0; --st) {
+        const double x = __shfl(v / dg[st], st, 16);
+        if (r == st) v = x;
+        if (r < st) v -= S[(o + st) * wp + o + r] * x;
+      }
+      if (o + r <= j) S[(o + r) * wp + j] = v;  // below X's diagonal: the U_ii copy
+    }
+    __syncthreads();
+  }
+}
+
+// LDS doubles the blocked Cholesky + inverse need for padded order wp.
+__host__ __device__ inline int blocked_lds_doubles(int wp) { return wp * wp + 16 * wp + 16; }
+
+// Order of the padded LDS matrix used by the blocked forms for order w.
+__host__ __device__ inline int blocked_order(int w) {
+  int wp = 16;
+  while (wp < w) wp *= 2;
+  return wp;
+}
+
 }  // namespace cqr

@@ -901,9 +901,9 @@ hipError_t launch_reduce(bool gram, double *part, int64_t nch, int p, int q, dou
 // ----------------------------------------------------------------------------
 // k_chol_inv: Cholesky W = U^T U of one panel's Gram matrix (Algorithm 1 /
 // Algorithm 8, Cholesky step) and the inverse U^{-1}, in one workgroup with
-// the whole w x w matrix in LDS. Right-looking, row-oriented (upper factor);
-// the inverse by a column sweep of back substitution U X = I, with X kept in
-// the (unused) strict lower triangle of the LDS matrix, transposed.
+// the whole matrix in LDS (padded with the identity to order 16 * 2^k).
+// Right-looking Cholesky by 16-column panels, then the blocked in-place
+// triangular inverse by block back substitution (device_common.h).
 // ----------------------------------------------------------------------------
 constexpr int kCholThreads = 512;
 
@@ -912,47 +912,43 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double *__restr
                                                            double *__restrict__ rblk, int64_t ldr,
                                                            double *__restrict__ uinv, int *info,
                                                            int col0) {
-  // S: w*w matrix (upper: W, then U; strict lower: X = U^{-1}, transposed);
-  // D: the diagonal of U, then of X
-  extern __shared__ double S[];
+  extern __shared__ double S[];  // wp x wp, then the inverse's scratch
+  __shared__ int flag;
   if (*info) return;
-  double *D = S + w * w;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < w * w; e += nt) {
-    const int i = e / w, j = e % w;
-    S[e] = (i <= j) ? W[e] : 0.0;
+  const int tid = threadIdx.x, nt = blockDim.x, wp = blocked_order(w);
+  for (int e = tid; e < wp * wp; e += nt) {
+    const int i = e / wp, j = e % wp;
+    S[e] = (i < w && j < w) ? ((i <= j) ? W[i * w + j] : 0.0) : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
-  const int fail = lds_cholesky(S, D, w);
+  const int fail = lds_cholesky_blocked(S, wp, &flag);
   if (fail) {
     if (tid == 0) atomicCAS(info, 0, col0 + fail);
     return;
   }
   for (int e = tid; e < w * w; e += nt) {
     const int i = e / w, j = e % w;
-    const double u = (i < j) ? S[e] : (i == j ? D[i] : 0.0);
+    const double u = (i <= j) ? S[i * wp + j] : 0.0;
     if (uout) uout[e] = u;
     if (rblk) rblk[i + (int64_t)j * ldr] = u;
   }
-  __syncthreads();  // D is reused for the diagonal of X below
-  // U's diagonal moves to S[k*w + k] for the inverse
-  for (int k = tid; k < w; k += nt) S[k * w + k] = D[k];
   __syncthreads();
-  lds_upper_inverse(S, D, w);
+  lds_upper_inverse_blocked(S, wp, S + wp * wp, S + wp * wp + 16 * wp);
   const int ldu = (int)padded_ld(w);
   for (int e = tid; e < w * ldu; e += nt) {
     const int i = e / ldu, c = e % ldu;
-    uinv[e] = (c < i || c >= w) ? 0.0 : (c == i ? D[i] : S[c * w + i]);
+    uinv[e] = (c < i || c >= w) ? 0.0 : S[i * wp + c];
   }
 }
 
 hipError_t launch_chol_inv(const double *W, int w, double *uout, double *rblk, int64_t ldr,
                            double *uinv, int *info, int col0, hipStream_t s) {
   if (w < 1 || w > kMaxPanel) return hipErrorInvalidValue;
-  const size_t lds = ((size_t)w * w + w) * sizeof(double);
+  const int wp = blocked_order(w);
+  const size_t lds = (size_t)blocked_lds_doubles(wp) * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {
-    const size_t most = ((size_t)kMaxPanel * kMaxPanel + kMaxPanel) * sizeof(double);
+    const size_t most = (size_t)blocked_lds_doubles(kMaxPanel) * sizeof(double);
     const hipError_t e = hipFuncSetAttribute((const void *)k_chol_inv,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)most);
     if (e != hipSuccess) return e;
@@ -972,30 +968,30 @@ hipError_t launch_chol_inv(const double *W, int w, double *uout, double *rblk, i
 __global__ __launch_bounds__(kCholThreads) void k_tri_inv(const double *__restrict__ R, int n,
                                                           int64_t sR, double *__restrict__ Rinv,
                                                           int64_t sRi) {
-  extern __shared__ double S[];
-  double *D = S + n * n;
+  extern __shared__ double S[];  // wp x wp, then the inverse's scratch
   R += blockIdx.x * sR;
   Rinv += blockIdx.x * sRi;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < n * n; e += nt) {
-    const int i = e / n, j = e % n;
-    S[e] = (i <= j) ? R[i + (int64_t)j * n] : 0.0;
+  const int tid = threadIdx.x, nt = blockDim.x, wp = blocked_order(n);
+  for (int e = tid; e < wp * wp; e += nt) {
+    const int i = e / wp, j = e % wp;
+    S[e] = (i < n && j < n) ? ((i <= j) ? R[i + (int64_t)j * n] : 0.0) : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
-  lds_upper_inverse(S, D, n);
+  lds_upper_inverse_blocked(S, wp, S + wp * wp, S + wp * wp + 16 * wp);
   for (int e = tid; e < n * n; e += nt) {
     const int i = e / n, c = e % n;
-    Rinv[e] = (c < i) ? 0.0 : (c == i ? D[i] : S[c * n + i]);
+    Rinv[e] = (c < i) ? 0.0 : S[i * wp + c];
   }
 }
 
 hipError_t launch_tri_inv(const double *R, int n, int64_t sR, double *Rinv, int64_t sRi, int batch,
                           hipStream_t s) {
   if (n < 1 || n > kMaxPanel) return hipErrorInvalidValue;
-  const size_t lds = ((size_t)n * n + n) * sizeof(double);
+  const int wp = blocked_order(n);
+  const size_t lds = (size_t)blocked_lds_doubles(wp) * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {
-    const size_t most = ((size_t)kMaxPanel * kMaxPanel + kMaxPanel) * sizeof(double);
+    const size_t most = (size_t)blocked_lds_doubles(kMaxPanel) * sizeof(double);
     const hipError_t e = hipFuncSetAttribute((const void *)k_tri_inv,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)most);
     if (e != hipSuccess) return e;

@@ -146,8 +146,12 @@ void cqr_plan_destroy(cqr_batch_plan *plan);
  * 1 <= n <= CQR_MAX_PANEL (R^{-1} is formed in one workgroup's LDS).
  * workspace: >= cqr_backward_workspace_bytes(m, n, batch) bytes of device
  * memory, 256-byte aligned, or NULL for a buffer the library keeps per device.
- * Asynchronous on `stream`; bitwise reproducible. Returns CQR_OK or a
- * negative status (argument errors before any device work). */
+ * Asynchronous on `stream`; bitwise reproducible. R^{-1} is computed on a
+ * library-owned side stream of default priority, forked from and joined back
+ * into `stream` with events, so it overlaps the first pass (a graph capture
+ * of `stream` records the fork and join; the first call on a device, which
+ * creates that stream, must not be made during a capture). Returns CQR_OK
+ * or a negative status (argument errors before any device work). */
 size_t cqr_backward_workspace_bytes(int64_t m, int64_t n, int64_t batch);
 int cqr_backward(int64_t m, int64_t n, const double *Q, const double *A, int64_t lda,
                  const double *R, const double *dQ, const double *dR, double *dA, void *stream,

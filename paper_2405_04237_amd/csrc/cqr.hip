@@ -108,6 +108,11 @@ struct DevState {
   int *info = nullptr;
   void *bwd = nullptr;  // backward workspace
   size_t bwd_bytes = 0;
+  // side stream (default priority) for independent small work, forked from
+  // and joined back into the caller's stream with events
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  std::mutex side;  // one fork/join sequence at a time on this device
 };
 std::mutex g_mu;
 std::map<int, DevState> g_dev;
@@ -615,6 +620,31 @@ int cqr_backward_batched(int64_t batch, int64_t m, int64_t n, const double *Q, c
                       [&] { return cqr::launch_zero2d(dA, m, n, lda, stride, b, s); }));
   hipError_t e = cqr::launch_set_int(info, 0, s);
   if (e != hipSuccess) return CQR_ERR_HIP;
+  // R^{-1} needs only R: it runs on the side stream while pass 1 streams
+  // over the rows, and is joined back before the n x n step
+  DevState *dev_state = nullptr;
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CQR_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState &d = g_dev[dev];
+    if (!d.aux) {
+      if (hipStreamCreateWithFlags(&d.aux, hipStreamNonBlocking) != hipSuccess) return CQR_ERR_HIP;
+      if (hipEventCreateWithFlags(&d.fork, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&d.join, hipEventDisableTiming) != hipSuccess)
+        return CQR_ERR_HIP;
+    }
+    dev_state = &d;
+  }
+  std::lock_guard<std::mutex> side_lock(dev_state->side);
+  hipStream_t aux = dev_state->aux;
+  if (hipEventRecord(dev_state->fork, s) != hipSuccess ||
+      hipStreamWaitEvent(aux, dev_state->fork, 0) != hipSuccess)
+    return CQR_ERR_HIP;
+  e = timed(aux, CQR_K_CHOL, bf * nf * nf * nf / 3.0, 16.0 * bf * nn,
+            [&] { return cqr::launch_tri_inv(R, ni, nn, Rinv, nn, b, aux); });
+  if (e != hipSuccess) return CQR_ERR_HIP;
+  if (hipEventRecord(dev_state->join, aux) != hipSuccess) return CQR_ERR_HIP;
   // pass 1: T = S^T dQ (upper 64x64 tiles), split over m, fixed-order reduce
   if (dQ) {
     e = timed(s, CQR_K_PROJ, bf * mf * nf * nf, 16.0 * bf * mf * nf, [&] {
@@ -628,10 +658,8 @@ int cqr_backward_batched(int64_t batch, int64_t m, int64_t n, const double *Q, c
     });
     if (e != hipSuccess) return CQR_ERR_HIP;
   }
-  // n x n part: R^{-1}, C = copyltu(M), the stacked right operand
-  e = timed(s, CQR_K_CHOL, bf * nf * nf * nf / 3.0, 16.0 * bf * nn,
-            [&] { return cqr::launch_tri_inv(R, ni, nn, Rinv, nn, b, s); });
-  if (e != hipSuccess) return CQR_ERR_HIP;
+  // n x n part: C = copyltu(M), the stacked right operand (after R^{-1})
+  if (hipStreamWaitEvent(s, dev_state->join, 0) != hipSuccess) return CQR_ERR_HIP;
   e = timed(s, CQR_K_SMALL, bf * 2.0 * nf * nf * nf, 8.0 * bf * 6 * nn, [&] {
     return cqr::launch_adj_small(ni, T, nn, R, dR, nn, Rinv, nn, dQ ? 1 : 0, recompute ? 1 : 0, C, G,
                                  nn, Y, lay.ldy, sy, dQ ? 1 : 0, b, s);

@@ -177,8 +177,123 @@ __global__ __launch_bounds__(64) void k_tn(int64_t m, int p, int q, const double
       }
 }
 
+// k_tn_wide: the projection form (not a Gram) with a 64 x 128 output tile
+// per wave (4 x 8 blocks: 256 accumulator registers, all in AGPRs) and a
+// two-stage register ring (128 MFMAs of cover per stage). Each 16-row step
+// loads 192 column segments for 128 MFMAs instead of 128 for 64, which moves
+// the kernel from load- to MFMA-bound. Lane maps as in k_tn.
+template <bool VEC>
+__global__ __launch_bounds__(64) void k_tn_wide(int64_t m, int p, int q, const double *__restrict__ L,
+                                                int64_t ldl, const double *__restrict__ Rt,
+                                                int64_t ldr, double *__restrict__ part, int64_t rc,
+                                                int tp, int tq, const int *__restrict__ info) {
+  if (*info) return;
+  const int64_t lid = xcd_logical(blockIdx.x, gridDim.x);
+  const int T = tp * tq;
+  const int64_t c = lid / T;
+  const int t = (int)(lid % T);
+  const int ti = t / tq, tj = t % tq;
+  const int lane = threadIdx.x, g = lane >> 4, cl = lane & 15;
+  const int i0 = ti * kTile, j0 = tj * 2 * kTile;
+  const int64_t rb = c * rc;
+  const int64_t re = (m < rb + rc) ? m : rb + rc;
+  const int64_t nsteps = (re - rb) / 16;
+  // out-of-range columns read column 0 (their outputs are never stored)
+  const double *pa[4];
+  const double *pb[8];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int ca = i0 + 16 * u + cl;
+    pa[u] = L + (int64_t)(ca < p ? ca : 0) * ldl + rb + 4 * g;
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int cb = j0 + 16 * u + cl;
+    pb[u] = Rt + (int64_t)(cb < q ? cb : 0) * ldr + rb + 4 * g;
+  }
+  d4 acc[4][8];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 8; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+  auto ld4 = [&](const double *ptr, double (&v)[4]) {
+    if (VEC) {
+      const double2 *x2 = reinterpret_cast<const double2 *>(ptr);
+      const double2 a = x2[0], b = x2[1];
+      v[0] = a.x;
+      v[1] = a.y;
+      v[2] = b.x;
+      v[3] = b.y;
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) v[s] = ptr[s];
+    }
+  };
+  auto load = [&](double (&da)[4][4], double (&db)[8][4], int64_t off) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ld4(pa[u] + off, da[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ld4(pb[u] + off, db[u]);
+  };
+  auto compute = [&](const double (&da)[4][4], const double (&db)[8][4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 8; ++y) acc[x][y] = mfma16x16x4(da[x][s], db[y][s], acc[x][y]);
+  };
+  double a0[4][4], b0[8][4];
+  if (nsteps > 0) {
+    double a1[4][4], b1[8][4];
+    auto at = [&](int64_t st) -> int64_t { return 16 * (st < nsteps ? st : nsteps - 1); };
+    load(a0, b0, 0);
+    int64_t it = 0;
+    for (; it + 2 <= nsteps; it += 2) {
+      load(a1, b1, at(it + 1));
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      load(a0, b0, at(it + 2));
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (it < nsteps) compute(a0, b0);
+  }
+  const int64_t rt = rb + 16 * nsteps;
+  if (rt < re) {  // ragged tail: rows rt + 4g + s < re only
+    const int64_t off = 16 * nsteps;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a0[u][s] = ((rt + 4 * g + s) < re) ? pa[u][off + s] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) b0[u][s] = ((rt + 4 * g + s) < re) ? pb[u][off + s] : 0.0;
+    compute(a0, b0);
+  }
+  double *out = part + (size_t)c * (size_t)p * (size_t)q;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 8; ++y)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int I = i0 + 16 * x + g + 4 * e, J = j0 + 16 * y + cl;
+        if (I < p && J < q) out[(size_t)I * q + J] = acc[x][y][e];
+      }
+}
+
+// the wide tile is used for single-matrix projections that fill it
+static bool tn_use_wide(bool gram, int p, int q, int batch) {
+  return !gram && batch == 1 && p >= kTile && q >= 2 * kTile;
+}
+
 int64_t tn_tiles(bool gram, int p, int q) {
   const int tp = (p + kTile - 1) / kTile, tq = (q + kTile - 1) / kTile;
+  if (tn_use_wide(gram, p, q, 1)) return (int64_t)tp * ((q + 2 * kTile - 1) / (2 * kTile));
   return gram ? (int64_t)tp * (tp + 1) / 2 : (int64_t)tp * tq;
 }
 
@@ -187,9 +302,20 @@ hipError_t launch_tn(bool gram, int64_t m, int p, int q, const double *L, int64_
                      const int *info, hipStream_t s, int batch, int64_t sL, int64_t sRt,
                      int64_t sPart) {
   const int tp = (p + kTile - 1) / kTile, tq = (q + kTile - 1) / kTile;
-  const int64_t nb = tn_tiles(gram, p, q) * nch;
   const bool vec = (ldl % 2 == 0) && (ldr % 2 == 0) && ((uintptr_t)L % 16 == 0) &&
                    ((uintptr_t)Rt % 16 == 0) && (rc % 16 == 0) && (sL % 2 == 0) && (sRt % 2 == 0);
+  if (tn_use_wide(gram, p, q, batch)) {
+    const int tqw = (q + 2 * kTile - 1) / (2 * kTile);
+    const dim3 gw((unsigned)((int64_t)tp * tqw * nch));
+    if (vec)
+      hipLaunchKernelGGL((k_tn_wide<true>), gw, dim3(64), 0, s, m, p, q, L, ldl, Rt, ldr, part, rc,
+                         tp, tqw, info);
+    else
+      hipLaunchKernelGGL((k_tn_wide<false>), gw, dim3(64), 0, s, m, p, q, L, ldl, Rt, ldr, part, rc,
+                         tp, tqw, info);
+    return hipGetLastError();
+  }
+  const int64_t nb = tn_tiles(gram, p, q) * nch;
   dim3 grid((unsigned)nb, (unsigned)batch), block(64);
 #define CQR_TN(U, V)                                                                             \
   hipLaunchKernelGGL((k_tn<U, V>), grid, block, 0, s, m, p, q, L, ldl, Rt, ldr, part, rc, tp, tq, \

@@ -100,10 +100,16 @@ size_t cqr_workspace_bytes(int64_t m, int64_t n, int64_t b, int schedule);
 int64_t cqr_default_panel(int64_t m, int64_t n, int schedule);
 
 /* Batched factorisation: many independent matrices of uneven shape in one
- * persistent launch. Each workgroup takes the next matrix from a queue
- * ordered longest-first (work ~ m n^2) and runs mCQR2GS (Algorithm 9) on it
- * alone, with its panel reductions over rows finished in the workgroup's
- * local memory (no cross-workgroup communication).
+ * persistent launch. Each workgroup takes the next work item from a queue
+ * ordered longest-first (work ~ m n^2) and runs mCQR2GS (Algorithm 9) on it,
+ * with its panel reductions over rows finished in the workgroup's local
+ * memory. A matrix whose work exceeds one workgroup's fair share is split by
+ * rows over a team of up to four workgroups that add their row-reduced
+ * products in a fixed member order through device memory (the paper's
+ * distributed form, Algorithm 8, with workgroups for ranks); every member
+ * repeats the small Cholesky steps. All workgroups of the launch are
+ * resident at once, so team members always find their partners; a wait
+ * that still exceeds a spin limit of a few seconds ends with info = -1.
  *
  * cqr_plan_batched (host shapes; allocates and synchronises, so call it
  * outside graph capture): h_m[i], h_n[i] the shape of matrix i, h_b[i] its
@@ -111,15 +117,17 @@ int64_t cqr_default_panel(int64_t m, int64_t n, int schedule);
  * form: n <= 128, panel width <= 32; schedule must be CQR_SCHED_MOD
  * (CQR_ERR_UNSUPPORTED otherwise).
  *
- * cqr_factor_batched enqueues a queue reset and one persistent kernel on
- * `stream` and nothing else: no allocation, no memset, no synchronisation,
+ * cqr_factor_batched enqueues a reset kernel (queue word, team counters) and
+ * one persistent kernel on `stream` and nothing else: no allocation, no
+ * memset, no synchronisation,
  * so the call can be captured into a HIP graph and replayed. d_A, d_lda,
  * d_Q, d_R are device arrays (indexed by matrix id) of device pointers and
  * leading dimensions: A_i and Q_i are m_i x n_i column-major with leading
  * dimension d_lda[i] >= m_i (Q_i may equal A_i), R_i is n_i x n_i
- * column-major with leading dimension n_i. d_info[i] receives 0 or the
- * 1-based breakdown column of matrix i (then Q_i, R_i are undefined). Calls
- * that use the same plan must not overlap in time (they share its queue). */
+ * column-major with leading dimension n_i. d_info[i] receives 0, the
+ * 1-based breakdown column of matrix i, or -1 (a team wait timed out); in
+ * both error cases Q_i and R_i are undefined. Calls that use the same plan
+ * must not overlap in time (they share its queue and team buffers). */
 typedef struct cqr_batch_plan cqr_batch_plan;
 int cqr_plan_batched(int64_t batch, const int64_t *h_m, const int64_t *h_n, const int64_t *h_b,
                      int schedule, cqr_batch_plan **plan);

@@ -44,7 +44,7 @@ __device__ inline Lds lds_layout(double *base) {
   L.ui = L.ub + kBB;
   L.s = L.ui + kBB + 64;
   L.d = L.s + kBB;
-  L.flag = reinterpret_cast<int *>(L.d + kBatchMaxPanel);
+  L.flag = reinterpret_cast<int *>(L.d + kBatchMaxPanel);  // flag[0]: slot, flag[1]: team wait
   return L;
 }
 
@@ -431,6 +431,58 @@ __device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, 
   wg_sync();
 }
 
+// Spin limit of a team barrier (s_sleep 2 per try, about 3 s in all): a
+// partner that never arrives ends the wait with an error, not a hang.
+constexpr int64_t kTeamSpins = int64_t(1) << 25;
+
+// A workgroup's share of one matrix: rows [r0, r0 + mloc) of the member-th of
+// `team` workgroups; part / cnt: the team's exchange buffer and counter.
+struct Team {
+  int64_t r0, mloc;
+  int member, team;
+  double *part;
+  int *cnt;
+  int barriers;  // team barriers passed so far
+};
+
+// out (LDS, count doubles: this member's partial sum over its rows) := the
+// sum of all members' partials, in member order, identical in every member.
+// Returns false if a partner did not arrive within the spin limit.
+__device__ bool team_reduce(const Lds &S, Team &T, double *out, int count) {
+  const int tid = threadIdx.x;
+  double *buf = T.part + (int64_t)(T.barriers & 1) * T.team * kTeamSlot;
+  double *mine = buf + (int64_t)T.member * kTeamSlot;
+  for (int e = tid; e < count; e += kThreads) mine[e] = out[e];
+  __threadfence();  // release this member's partial (all L2s)
+  __syncthreads();
+  if (tid == 0) {
+    const int target = T.team * (T.barriers + 1);
+    atomicAdd(T.cnt, 1);
+    int ok = 0;
+    for (int64_t i = 0; i < kTeamSpins; ++i) {
+      if (__hip_atomic_load(T.cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) {
+        ok = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    S.flag[1] = ok;
+  }
+  __syncthreads();
+  const bool ok = S.flag[1] != 0;
+  __threadfence();  // acquire the partners' partials
+  if (ok) {
+    for (int e = tid; e < count; e += kThreads) {
+      double x = 0.0;
+      for (int k = 0; k < T.team; ++k) x += buf[(int64_t)k * kTeamSlot + e];
+      out[e] = x;
+    }
+  }
+  __syncthreads();
+  ++T.barriers;
+  return ok;
+}
+
 // Cholesky of W (LDS, row-major w x w, upper read) into uout (row-major, ld
 // w) and its inverse into ui (row-major, ld ldu). Returns the failing 1-based
 // panel column or 0 (uniform over the workgroup).
@@ -475,10 +527,15 @@ __device__ __forceinline__ void wg_r_upper_product(double *R, int n, int r0, int
 
 // mCQR2GS of one matrix by one workgroup, as a sequence of phases with one
 // call site per streaming primitive. Returns 0 or the breakdown column.
-__device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int64_t m, int n, int b, const double *A,
-                                          int64_t lda, double *Q, double *R) {
+__device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int n, int b, const double *A0,
+                                          int64_t lda, double *Q0, double *R, Team &T) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += kThreads) R[e] = 0.0;
+  const bool lead = T.member == 0;  // the member that writes R
+  const int64_t m = T.mloc;         // this workgroup's rows: [T.r0, T.r0 + m)
+  const double *A = A0 + T.r0;
+  double *Q = Q0 + T.r0;
+  if (lead)
+    for (int e = tid; e < n * n; e += kThreads) R[e] = 0.0;
   const int w0 = n < b ? n : b;
   int s = 0;  // first column of the current panel
   int w = w0;
@@ -504,7 +561,7 @@ __device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int64_t m, int n, int b,
       case 4: { const int f = wg_chol_inv(S, w, S.ub, ldw); if (f) return f; break; }
       case 5: op = 2; np = nq = w; nL = Q; nY = S.ui; nldy = ldw; nC = Q; break;
       case 6:
-        wg_r_upper_product(R, n, 0, w, S.ub, S.ua);
+        if (lead) wg_r_upper_product(R, n, 0, w, S.ub, S.ua);
         next = true;
         break;
       // panel s >= b: Y := Q_{j-1}^T A_{:,j:k}; R_{j-1,j:k} := Y; A_{:,j:k} -= Q_{j-1} Y
@@ -516,7 +573,7 @@ __device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int64_t m, int n, int b,
         const int ldy = (int)padded_ld(nr);
         for (int e = tid; e < b * nr; e += kThreads) {
           const int i = e / nr, j = e % nr;
-          R[(ps + i) + (int64_t)(s + j) * n] = S.y[i * ldy + j];
+          if (lead) R[(ps + i) + (int64_t)(s + j) * n] = S.y[i * ldy + j];
           S.y[i * ldy + j] = -S.y[i * ldy + j];
         }
         __syncthreads();
@@ -534,7 +591,7 @@ __device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int64_t m, int n, int b,
       case 13: op = 1; ta = w; tb = s; tA = Xj; tB = Q; tout = S.y; tldo = ldw; ttrans = true; break;
       case 14: {
         // R_{1:j-1,j} += Z Ua; then Y := -Z for the update
-        for (int e = tid; e < s * w; e += kThreads) {
+        for (int e = tid; lead && e < s * w; e += kThreads) {
           const int i = e % s, c = e / s;
           double acc = 0.0;
           for (int k = 0; k <= c; ++k) acc += S.y[i * ldw + k] * S.ua[k * w + c];
@@ -551,13 +608,14 @@ __device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int64_t m, int n, int b,
       case 17: { const int f = wg_chol_inv(S, w, S.ub, ldw); if (f) return s + f; break; }
       case 18: op = 2; np = nq = w; nL = Xj; nY = S.ui; nldy = ldw; nC = Xj; break;
       case 19:
-        wg_r_upper_product(R, n, s, w, S.ub, S.ua);
+        if (lead) wg_r_upper_product(R, n, s, w, S.ub, S.ua);
         __syncthreads();
         next = true;
         break;
     }
     if (op == 1) {
       wg_tn(tm, ta, tb, tA, lda, tB, lda, tout, tldo, ttrans);
+      if (T.team > 1 && !team_reduce(S, T, tout, (ttrans ? tb : ta) * tldo)) return -1;
     } else if (op == 2) {
       wg_nn(tm, np, nq, nL, lda, nY, nldy, nCin ? nCin : nC, lda, nC, lda, nsub);
     }
@@ -572,25 +630,41 @@ __device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int64_t m, int n, int b,
   }
 }
 
-__global__ void k_set_int_batched(int *p) { *p = 0; }
+// queue word and team counters to zero (a kernel, so that graphs replay it)
+__global__ void k_reset_batched(int *queue, int *cnt, int ncnt) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncnt; i += gridDim.x * blockDim.x) cnt[i] = 0;
+}
 
 __global__ __launch_bounds__(kThreads) void k_batched_mod(
-    const int *__restrict__ order, const int64_t *__restrict__ ms, const int *__restrict__ ns,
-    const int *__restrict__ bs, int count, const double *const *__restrict__ dA,
+    const BatchSlot *__restrict__ slots, int nslots, const int64_t *__restrict__ ms,
+    const int *__restrict__ ns, const int *__restrict__ bs, const double *const *__restrict__ dA,
     const int64_t *__restrict__ dlda, double *const *__restrict__ dQ, double *const *__restrict__ dR,
-    int *__restrict__ dinfo, int *queue) {
+    int *__restrict__ dinfo, int *queue, double *team_part, int *team_cnt) {
   extern __shared__ double lds[];
   const Lds S = lds_layout(lds);
   const int tid = threadIdx.x;
   for (;;) {
-    if (tid == 0) *S.flag = atomicAdd(queue, 1);
+    if (tid == 0) S.flag[0] = atomicAdd(queue, 1);
     __syncthreads();
-    const int slot = *S.flag;
+    const int slot = S.flag[0];
     __syncthreads();
-    if (slot >= count) break;  // uniform: every wave leaves together
-    const int i = order[slot];
-    const int fail = wg_mcqr2gs(S, ms[i], ns[i], bs[i], dA[i], dlda[i], dQ[i], dR[i]);
-    if (tid == 0) dinfo[i] = fail;
+    if (slot >= nslots) break;  // uniform: every wave leaves together
+    const BatchSlot sl = slots[slot];
+    const int i = sl.matrix;
+    const int64_t m = ms[i];
+    Team T;
+    T.member = sl.member;
+    T.team = sl.team;
+    // members take equal 64-row-aligned shares; the last takes the rest
+    const int64_t share = (m / sl.team) / 64 * 64;
+    T.r0 = share * sl.member;
+    T.mloc = (sl.member == sl.team - 1) ? m - T.r0 : share;
+    T.part = team_part + sl.part;
+    T.cnt = team_cnt + sl.cnt;
+    T.barriers = 0;
+    const int fail = wg_mcqr2gs(S, ns[i], bs[i], dA[i], dlda[i], dQ[i], dR[i], T);
+    if (tid == 0 && sl.member == 0) dinfo[i] = fail;
     wg_sync();
   }
 }
@@ -601,9 +675,10 @@ size_t batched_lds_bytes() {
   return (size_t)(kYSize + 4 * kBB + 64 + kBB + kBatchMaxPanel) * sizeof(double) + 64;
 }
 
-hipError_t launch_batched_mod(int grid, const int *order, const int64_t *ms, const int *ns,
-                              const int *bs, int count, const double *const *dA, const int64_t *dlda,
-                              double *const *dQ, double *const *dR, int *dinfo, int *queue,
+hipError_t launch_batched_mod(int grid, const BatchSlot *slots, int nslots, const int64_t *ms,
+                              const int *ns, const int *bs, const double *const *dA,
+                              const int64_t *dlda, double *const *dQ, double *const *dR,
+                              int *dinfo, int *queue, double *team_part, int *team_cnt, int nteams,
                               hipStream_t s) {
   static bool attr_set = false;
   const size_t lds = batched_lds_bytes();
@@ -613,11 +688,11 @@ hipError_t launch_batched_mod(int grid, const int *order, const int64_t *ms, con
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_set_int_batched, dim3(1), dim3(1), 0, s, queue);
+  hipLaunchKernelGGL(k_reset_batched, dim3(1), dim3(256), 0, s, queue, team_cnt, nteams);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batched_mod, dim3((unsigned)grid), dim3(kThreads), lds, s, order, ms, ns, bs,
-                     count, dA, dlda, dQ, dR, dinfo, queue);
+  hipLaunchKernelGGL(k_batched_mod, dim3((unsigned)grid), dim3(kThreads), lds, s, slots, nslots, ms,
+                     ns, bs, dA, dlda, dQ, dR, dinfo, queue, team_part, team_cnt);
   return hipGetLastError();
 }
 

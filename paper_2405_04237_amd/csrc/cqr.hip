@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <numeric>
 #include <map>
 #include <mutex>
@@ -694,12 +695,15 @@ struct cqr_batch_plan {
   int64_t count = 0;
   int device = 0;
   int grid = 0;
-  void *mem = nullptr;  // order | m | n | b | queue
-  int *order = nullptr;
+  int nslots = 0, nteams = 0;
+  void *mem = nullptr;  // slots | m | n | b | queue | team counters | team partials
+  cqr::BatchSlot *slots = nullptr;
   int64_t *m = nullptr;
   int *n = nullptr;
   int *b = nullptr;
   int *queue = nullptr;
+  int *team_cnt = nullptr;
+  double *team_part = nullptr;
   double flops = 0, bytes = 0;
 };
 
@@ -730,44 +734,76 @@ int cqr_plan_batched(int64_t batch, const int64_t *h_m, const int64_t *h_n, cons
     flops += 2.0 * mf * nf * nf - 2.0 * nf * nf * nf / 3.0;  // Householder-equivalent
     bytes += 24.0 * mf * nf + 24.0 * mf * nf * nf / be;
   }
-  // longest processing time first: work ~ m n^2, ties by index
+  int cus = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return CQR_ERR_HIP;
+  const int64_t resident = std::max<int64_t>(1, (int64_t)cus * cqr::batched_blocks_per_cu());
+  // Teams: a matrix whose work (~ m n^2) exceeds a resident workgroup's fair
+  // share is split by rows over up to kBatchMaxTeam workgroups (at least
+  // 2048 rows each), so that no single matrix sets the makespan.
+  std::vector<double> work(batch);
+  double total = 0;
+  for (int64_t i = 0; i < batch; ++i) total += (work[i] = (double)m[i] * n[i] * n[i]);
+  const double share = total / (double)std::min<int64_t>(batch, resident);
+  std::vector<int> team(batch, 1);
+  for (int64_t i = 0; i < batch; ++i) {
+    int t = (int)std::ceil(work[i] / share - 1e-9);
+    t = std::min<int64_t>({(int64_t)std::max(t, 1), (int64_t)cqr::kBatchMaxTeam, resident,
+                           std::max<int64_t>(1, m[i] / 2048)});
+    team[i] = t;
+  }
+  // longest processing time first: per-member work, ties by index
   std::vector<int> order(batch);
   std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    return (double)m[x] * n[x] * n[x] > (double)m[y] * n[y] * n[y];
-  });
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return work[x] / team[x] > work[y] / team[y]; });
+  std::vector<cqr::BatchSlot> slots;
+  int64_t nteams = 0, part_doubles = 0;
+  for (int i : order) {
+    const int t = team[i];
+    const int ci = (t > 1) ? (int)nteams++ : 0;
+    const int64_t po = (t > 1) ? part_doubles : 0;
+    if (t > 1) part_doubles += 2LL * t * cqr::kTeamSlot;
+    for (int k = 0; k < t; ++k) slots.push_back({i, k, t, ci, po});
+  }
+  const int64_t nslots = (int64_t)slots.size();
   cqr_batch_plan *pl = new cqr_batch_plan();
   pl->count = batch;
-  if (hipGetDevice(&pl->device) != hipSuccess) {
-    delete pl;
-    return CQR_ERR_HIP;
-  }
-  const size_t so = round_up(4 * batch, kAlign), sm = round_up(8 * batch, kAlign);
+  pl->device = dev;
+  pl->nslots = (int)nslots;
+  pl->nteams = (int)nteams;
+  const size_t ss = round_up(sizeof(cqr::BatchSlot) * nslots, kAlign), sm = round_up(8 * batch, kAlign);
   const size_t sn = round_up(4 * batch, kAlign), sb = round_up(4 * batch, kAlign);
-  if (hipMalloc(&pl->mem, so + sm + sn + sb + kAlign) != hipSuccess) {
+  const size_t sq = kAlign, sc = round_up(4 * std::max<int64_t>(nteams, 1), kAlign);
+  const size_t sp = round_up(8 * std::max<int64_t>(part_doubles, 1), kAlign);
+  if (hipMalloc(&pl->mem, ss + sm + sn + sb + sq + sc + sp) != hipSuccess) {
     delete pl;
     return CQR_ERR_NOMEM;
   }
   char *base = (char *)pl->mem;
-  pl->order = (int *)base;
-  pl->m = (int64_t *)(base + so);
-  pl->n = (int *)(base + so + sm);
-  pl->b = (int *)(base + so + sm + sn);
-  pl->queue = (int *)(base + so + sm + sn + sb);
-  bool ok = hipMemcpy(pl->order, order.data(), 4 * batch, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(pl->m, m.data(), 8 * batch, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(pl->n, n.data(), 4 * batch, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(pl->b, b.data(), 4 * batch, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemset(pl->queue, 0, sizeof(int)) == hipSuccess;
-  int cus = 0;
-  ok = ok && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) ==
-                 hipSuccess;
+  pl->slots = (cqr::BatchSlot *)base;
+  pl->m = (int64_t *)(base + ss);
+  pl->n = (int *)(base + ss + sm);
+  pl->b = (int *)(base + ss + sm + sn);
+  pl->queue = (int *)(base + ss + sm + sn + sb);
+  pl->team_cnt = (int *)(base + ss + sm + sn + sb + sq);
+  pl->team_part = (double *)(base + ss + sm + sn + sb + sq + sc);
+  const bool ok =
+      hipMemcpy(pl->slots, slots.data(), sizeof(cqr::BatchSlot) * nslots, hipMemcpyHostToDevice) ==
+          hipSuccess &&
+      hipMemcpy(pl->m, m.data(), 8 * batch, hipMemcpyHostToDevice) == hipSuccess &&
+      hipMemcpy(pl->n, n.data(), 4 * batch, hipMemcpyHostToDevice) == hipSuccess &&
+      hipMemcpy(pl->b, b.data(), 4 * batch, hipMemcpyHostToDevice) == hipSuccess &&
+      hipMemset(pl->queue, 0, sizeof(int)) == hipSuccess;
   if (!ok) {
     (void)hipFree(pl->mem);
     delete pl;
     return CQR_ERR_HIP;
   }
-  pl->grid = (int)std::min<int64_t>(batch, (int64_t)cus * cqr::batched_blocks_per_cu());
+  // every workgroup of the grid is resident at once, so team members that
+  // wait for each other always find their partners running
+  pl->grid = (int)std::min<int64_t>(nslots, resident);
   pl->flops = flops;
   pl->bytes = bytes;
   *plan = pl;
@@ -779,8 +815,9 @@ int cqr_factor_batched(const cqr_batch_plan *plan, const double *const *d_A, con
   if (!plan || !d_A || !d_lda || !d_Q || !d_R || !d_info) return CQR_ERR_ARG;
   hipStream_t s = (hipStream_t)stream;
   const hipError_t e = timed(s, CQR_K_BATCHED, plan->flops, plan->bytes, [&] {
-    return cqr::launch_batched_mod(plan->grid, plan->order, plan->m, plan->n, plan->b,
-                                   (int)plan->count, d_A, d_lda, d_Q, d_R, d_info, plan->queue, s);
+    return cqr::launch_batched_mod(plan->grid, plan->slots, plan->nslots, plan->m, plan->n,
+                                   plan->b, d_A, d_lda, d_Q, d_R, d_info, plan->queue,
+                                   plan->team_part, plan->team_cnt, plan->nteams, s);
   });
   return e == hipSuccess ? CQR_OK : CQR_ERR_HIP;
 }

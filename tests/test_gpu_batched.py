@@ -109,3 +109,25 @@ def test_batched_workload_shape_sample():
     for i in range(0, len(probs), 64):
         p = probs[i]
         _check(to_host(mats[i]), to_host(qs[i]), to_host(rs[i]), p.b, p.kappa)
+
+
+def test_batched_teams_breakdown_and_determinism():
+    """Matrices whose work exceeds a workgroup's fair share are split by rows
+    over a team of workgroups (here the 65536 x 128 matrix over four, the
+    60000 x 64 one over two). Every member takes the same Cholesky
+    decisions, so a breakdown column is still reported exactly; team sums go
+    through a fixed member order, so two runs agree bit for bit; the results
+    meet the oracle bounds."""
+    specs = [(65536, 128, 32, 1e12), (60000, 64, 32, 10.0)] + [(4096, 32, 16, 1e6)] * 6
+    mats = [matgen.test_matrix(m, n, k, seed=700 + i) for i, (m, n, b, k) in enumerate(specs)]
+    mats[1][:, 37] = 0.0
+    runs = []
+    for _ in range(2):
+        qs, rs, info = cqr.qr_batched([to_dev(a) for a in mats], bs=[s[2] for s in specs], check=False)
+        torch.cuda.synchronize()
+        runs.append(([to_host(q) for q in qs], [to_host(r) for r in rs], info.cpu().tolist()))
+    (q1, r1, i1), (q2, r2, i2) = runs
+    assert i1 == i2 == [0, 38, 0, 0, 0, 0, 0, 0]
+    for i in (0, 2, 3, 4, 5, 6, 7):
+        assert np.array_equal(q1[i], q2[i]) and np.array_equal(r1[i], r2[i])
+        _check(mats[i], q1[i], r1[i], specs[i][2], specs[i][3])

@@ -648,13 +648,14 @@ int cqr_backward_batched(int64_t batch, int64_t m, int64_t n, const double *Q, c
   if (hipEventRecord(dev_state->join, aux) != hipSuccess) return CQR_ERR_HIP;
   // pass 1: T = S^T dQ (upper 64x64 tiles), split over m, fixed-order reduce
   if (dQ) {
+    const bool upper = true;
     e = timed(s, CQR_K_PROJ, bf * mf * nf * nf, 16.0 * bf * mf * nf, [&] {
-      return cqr::launch_tn(true, m, ni, ni, S, lda, dQ, lda, part, lay.rc, lay.nch, info, s, b,
+      return cqr::launch_tn(upper, m, ni, ni, S, lda, dQ, lda, part, lay.rc, lay.nch, info, s, b,
                             stride, stride, lay.nch * nn);
     });
     if (e != hipSuccess) return CQR_ERR_HIP;
     e = timed(s, CQR_K_REDUCE, bf * lay.nch * nn, 8.0 * bf * (lay.nch + 1) * nn, [&] {
-      return cqr::launch_reduce(true, part, lay.nch, ni, ni, T, n, nullptr, 0, false, info, s, b,
+      return cqr::launch_reduce(upper, part, lay.nch, ni, ni, T, n, nullptr, 0, false, info, s, b,
                                 lay.nch * nn, nn, 0);
     });
     if (e != hipSuccess) return CQR_ERR_HIP;

@@ -797,6 +797,130 @@ __global__ __launch_bounds__(512, 1) void k_trsm(int64_t mfull, int w, double *X
   if (t + 1 < T) step(b1);
 }
 
+// ----------------------------------------------------------------------------
+// k_nn_ys: C = [L(:, 0:psplit) | L2] Y without an input C (the adjoint's
+// second pass, dA = [dQ | Q] [R^{-T}; G]), with Y staged per 64-column slab
+// in LDS as in k_upd: eight waves per workgroup (two per SIMD; one workgroup
+// per CU holds a slab of up to 256 x 64 doubles) sweep 32-row tiles of an
+// equal share of the rows. p and psplit are multiples of 16, so each 16-wide
+// k step reads one source. Batch: matrix blockIdx.y at the given strides.
+// ----------------------------------------------------------------------------
+constexpr int kYsMaxK = 256;
+
+__global__ __launch_bounds__(512, 1) void k_nn_ys(int64_t m, int p, int q, const double *L,
+                                                  int64_t ldl, const double *L2, int64_t ldl2,
+                                                  int psplit, const double *__restrict__ Y,
+                                                  int64_t ldy, double *C, int64_t ldc, int nslab,
+                                                  int64_t rows_per_wg, int64_t sL, int64_t sL2,
+                                                  int64_t sY, int64_t sC,
+                                                  const int *__restrict__ info) {
+  extern __shared__ double ys[];  // [p][64], row-major
+  if (*info) return;
+  {
+    const int64_t bi = blockIdx.y;
+    L += bi * sL;
+    L2 += bi * sL2;
+    Y += bi * sY;
+    C += bi * sC;
+  }
+  const int64_t lid = xcd_logical(blockIdx.x, gridDim.x);
+  const int c0 = (int)(lid % nslab) * kTile;
+  const int64_t rb = (lid / nslab) * rows_per_wg;
+  if (rb >= m) return;  // whole workgroup
+  const int64_t re = (rb + rows_per_wg < m) ? rb + rows_per_wg : m;
+  for (int e = threadIdx.x; e < p * kTile; e += 512) {
+    const int k = e / kTile, c = c0 + e % kTile;
+    ys[e] = (c < q) ? Y[(int64_t)k * ldy + c] : 0.0;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const double *yl = ys + 4 * cl;
+  const int nit = p / 16;
+  for (int64_t r0 = rb + 32 * wave; r0 < re; r0 += 256) {
+    const int64_t rl = r0 + 2 * cl;
+    const bool full = r0 + 32 <= m;
+    d4 acc[4][2];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+    auto lptr = [&](int kk) -> const double * {  // column kk + g of [L | L2], row rl
+      return (kk < psplit) ? L + (int64_t)(kk + g) * ldl + rl
+                           : L2 + (int64_t)(kk - psplit + g) * ldl2 + rl;
+    };
+    auto load = [&](double (&db)[4][2], int kk) {
+      const double *pl = lptr(kk);
+      const int64_t ld = (kk < psplit) ? ldl : ldl2;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if (full) {
+          const double2 t = *reinterpret_cast<const double2 *>(pl + (int64_t)(4 * s) * ld);
+          db[s][0] = t.x;
+          db[s][1] = t.y;
+        } else {
+          db[s][0] = (rl < m) ? pl[(int64_t)(4 * s) * ld] : 0.0;
+          db[s][1] = (rl + 1 < m) ? pl[(int64_t)(4 * s) * ld + 1] : 0.0;
+        }
+      }
+    };
+    double ya[4][4];
+    auto step = [&](const double (&db)[4][2], int kk) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = kk + 4 * s + g;
+        const double2 y0 = *reinterpret_cast<const double2 *>(yl + k * kTile);
+        const double2 y1 = *reinterpret_cast<const double2 *>(yl + k * kTile + 2);
+        ya[s][0] = y0.x;
+        ya[s][1] = y0.y;
+        ya[s][2] = y1.x;
+        ya[s][3] = y1.y;
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x4(ya[s][x], db[s][y], acc[x][y]);
+    };
+    double b0[4][2], b1[4][2], b2[4][2];
+    auto at = [&](int st) -> int { return 16 * (st < nit ? st : nit - 1); };
+    load(b0, 0);
+    load(b1, at(1));
+    int it = 0;
+    for (; it + 3 <= nit; it += 3) {
+      load(b2, at(it + 2));
+      __builtin_amdgcn_sched_barrier(0);
+      step(b0, 16 * it);
+      __builtin_amdgcn_sched_barrier(0);
+      load(b0, at(it + 3));
+      __builtin_amdgcn_sched_barrier(0);
+      step(b1, 16 * (it + 1));
+      __builtin_amdgcn_sched_barrier(0);
+      load(b1, at(it + 4));
+      __builtin_amdgcn_sched_barrier(0);
+      step(b2, 16 * (it + 2));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (it < nit) step(b0, 16 * it);
+    if (it + 1 < nit) step(b1, 16 * (it + 1));
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int col = c0 + 4 * g + 16 * e + x;
+        if (col < q) {
+          double *pc = C + (int64_t)col * ldc + rl;
+          if (full) {
+            *reinterpret_cast<double2 *>(pc) = double2{acc[x][0][e], acc[x][1][e]};
+          } else {
+            if (rl < m) pc[0] = acc[x][0][e];
+            if (rl + 1 < m) pc[1] = acc[x][1][e];
+          }
+        }
+      }
+  }
+}
+
 // rows of C per workgroup row-slab is 16 * RB * WR
 constexpr int kNnRB = 2;
 
@@ -821,6 +945,35 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
   const int wc = slabs >= 4 ? 4 : (slabs >= 2 ? 2 : 1);
   const int wr = 4 / wc;
   const int ncg = (slabs + wc - 1) / wc;
+  if (!subtract && !upper_y && C2 == nullptr && p <= kYsMaxK && p % 16 == 0 && psplit % 16 == 0 &&
+      (ldl % 2 == 0) && (ldl2 % 2 == 0) && (ldc % 2 == 0) && ((uintptr_t)L % 16 == 0) &&
+      ((uintptr_t)L2 % 16 == 0) && ((uintptr_t)C % 16 == 0) && (sL % 2 == 0) &&
+      (sL2 % 2 == 0) && (sC % 2 == 0)) {
+    // no input C, inner dimension <= 256: Y staged in LDS, one 8-wave
+    // workgroup per CU, rows shared equally among a slab's workgroups
+    static bool attr = false;
+    static int cus = 0;
+    if (!attr) {
+      hipError_t e = hipFuncSetAttribute((const void *)k_nn_ys,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         kYsMaxK * kTile * (int)sizeof(double));
+      if (e != hipSuccess) return e;
+      int dev = 0;
+      e = hipGetDevice(&dev);
+      if (e != hipSuccess) return e;
+      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return e;
+      attr = true;
+    }
+    const int64_t per = std::max<int64_t>(1, (int64_t)std::max(cus, 1) / ((int64_t)slabs * batch));
+    int64_t rpw = (m + per - 1) / per;
+    rpw = (rpw + 31) / 32 * 32;
+    const int64_t chunks = (m + rpw - 1) / rpw;
+    hipLaunchKernelGGL(k_nn_ys, dim3((unsigned)(chunks * slabs), (unsigned)batch), dim3(512),
+                       (size_t)p * kTile * sizeof(double), s, m, p, q, L, ldl, L2, ldl2, psplit, Y,
+                       ldy, C, ldc, slabs, rpw, sL, sL2, sY, sC, info);
+    return hipGetLastError();
+  }
   if (!subtract && ncg != 1) return hipErrorInvalidValue;  // in-place needs one column group
   if (!subtract && upper_y && batch == 1 && p == q && (q == 64 || q == 128) &&
       m >= (q == 128 ? 128 : 256) && L == C &&

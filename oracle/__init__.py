@@ -6,9 +6,11 @@ check and the benchmark's CPU-baseline leg may import it; the product path
 never does. It shares no code with the GPU library.
 """
 from .cholqr import (Breakdown, gram, xprod, chol_upper, cqr, cqr2, cqrgs, cqr2gs,
-                  mcqr2gs, qr_adjoint, householder_qr)
+                  mcqr2gs, qr_adjoint, householder_qr, frobenius_sq, scqr_shift, scqr,
+                  scqr3, UNIT_ROUNDOFF)
 from .metrics import orthogonality, residual, rel_fro
 
 __all__ = ["Breakdown", "gram", "xprod", "chol_upper", "cqr", "cqr2", "cqrgs",
            "cqr2gs", "mcqr2gs", "qr_adjoint", "householder_qr", "orthogonality",
-           "residual", "rel_fro"]
+           "residual", "rel_fro", "frobenius_sq", "scqr_shift", "scqr", "scqr3",
+           "UNIT_ROUNDOFF"]

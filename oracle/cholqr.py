@@ -1,4 +1,5 @@
-"""Oracle algorithms: CholeskyQR, CholeskyQR2, CQRGS, CQR2GS and mCQR2GS.
+"""Oracle algorithms: CholeskyQR, CholeskyQR2, shifted CholeskyQR and
+shifted CholeskyQR3, CQRGS, CQR2GS and mCQR2GS.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring). Plain FP64 NumPy/SciPy,
 one step per line of the paper's algorithms, no blocking or fusion beyond
@@ -18,6 +19,10 @@ Readings of the paper where it is silent:
 * The second CQRGS pass of CQR2GS uses the same panel width as the first.
 * mCQR2GS (Algorithm 9) leaves R implicit; R is assembled as derived in
   ``mcqr2gs``.
+* Shifted CholeskyQR (Algorithm 4): u is the unit roundoff of IEEE binary64,
+  2^-53. ||A||_F^2 is the sum of the squared entries, per CHUNK-row block and
+  then over blocks in the pairwise tree (the per-rank sums of section
+  "Shifted CholeskyQR3").
 """
 from __future__ import annotations
 
@@ -103,6 +108,44 @@ def cqr2(x: np.ndarray, col0: int = 0):
     """CholeskyQR2, Algorithm 3: CQR twice, R = R2 R1."""
     q1, r1 = cqr(x, col0)
     q, r2 = cqr(q1, col0)
+    return q, r2 @ r1
+
+
+UNIT_ROUNDOFF = 2.0 ** -53
+
+
+def frobenius_sq(x: np.ndarray) -> float:
+    """||X||_F^2: squares of the entries summed per CHUNK-row block, the block
+    sums added in the pairwise tree (section "Shifted CholeskyQR3": each rank
+    sums the squares of its rows, rank 0 adds the sums)."""
+    m = x.shape[0]
+    if m == 0:
+        return 0.0
+    parts = [np.array(np.sum(x[i:i + CHUNK] * x[i:i + CHUNK])) for i in range(0, m, CHUNK)]
+    return float(_pairwise(parts))
+
+
+def scqr_shift(x: np.ndarray) -> float:
+    """The shift s = sqrt(m) u ||X||_F^2 of Algorithm 4."""
+    return float(np.sqrt(x.shape[0]) * UNIT_ROUNDOFF * frobenius_sq(x))
+
+
+def scqr(x: np.ndarray, col0: int = 0):
+    """Shifted CholeskyQR, Algorithm 4: G = X^T X, W = G + sI, W = R^T R,
+    Q = X R^{-1}. Returns Q, R."""
+    g = gram(x)
+    s = scqr_shift(x)
+    w = g + s * np.eye(g.shape[0])
+    r = chol_upper(w, col0)
+    q = _right_solve_upper(x, r)
+    return q, r
+
+
+def scqr3(x: np.ndarray):
+    """Shifted CholeskyQR3, Algorithm 5: [Q1, R1] = sCQR(X);
+    [Q, R2] = CQR2(Q1); R = R2 R1."""
+    q1, r1 = scqr(x)
+    q, r2 = cqr2(q1)
     return q, r2 @ r1
 
 

@@ -5,6 +5,9 @@
   environment", subsection "Software"). Throughput is reported as this count
   divided by time ("Householder-equivalent" FLOP/s).
 * ``cqr2gs_table2``: Table 2's total for CQR2GS at P = 1.
+* ``cqr2_flops`` and ``scqr3_flops``: Table 1's CholeskyQR2 count and the
+  shifted CholeskyQR3 cost equation (subsection "Shifted CholeskyQR3"), both
+  at P = 1.
 * Per-step algorithmic counts, following Tables 1 and 2: a Gram of an m x w
   panel costs m w^2 (syrk), forming Q = X U^{-1} costs m w^2 (trsm), a
   projection Y = Q^T Z or an update Z -= Q Y with Q m x p and Z m x q costs
@@ -20,6 +23,14 @@ def householder_flops(m: int, n: int) -> float:
 
 def cqr2gs_table2(m: int, n: int, b: int) -> float:
     return 2.0 * b * b * n / 3.0 + n ** 3 / 3.0 + 4.0 * m * n * n
+
+
+def cqr2_flops(m: int, n: int) -> float:
+    return float(n) ** 3 + 4.0 * m * n * n
+
+
+def scqr3_flops(m: int, n: int) -> float:
+    return 5.0 * n ** 3 / 3.0 + 6.0 * m * n * n + 2.0 * m * n
 
 
 def panels(n: int, b: int):
@@ -70,6 +81,9 @@ def schedule_steps(m: int, n: int, b: int, schedule: str):
                       ("gram", m, w, 0), ("trsm", m, w, 0),
                       ("proj", m, s, w), ("update", m, s, w),
                       ("gram", m, w, 0), ("trsm", m, w, 0)]
+    elif schedule == "scqr3":
+        # sCQR, then CholeskyQR2 of its Q: three whole-matrix Gram + trsm passes
+        steps += [("gram", m, n, 0), ("trsm", m, n, 0)] * 3
     else:
         raise ValueError(schedule)
     return steps
@@ -79,6 +93,8 @@ def schedule_flops(m: int, n: int, b: int, schedule: str) -> float:
     f = sum(step_flops(k, mm, p, q) for k, mm, p, q in schedule_steps(m, n, b, schedule))
     if schedule == "orig":
         f += n ** 3 / 3.0  # R = R2 R1
+    elif schedule == "scqr3":
+        f += 2.0 * n ** 3 / 3.0  # R = (R3 R2) R1
     return f
 
 

@@ -170,6 +170,64 @@ def bench_backward(steps: int, warmup: int):
     return out
 
 
+def bench_scqr3(steps: int, warmup: int):
+    """Shifted CholeskyQR3 (Algorithm 5) at 2^22 x 128, kappa = 1e12 (past
+    CholeskyQR2's limit, within the shifted algorithm's reach at this m),
+    beside mCQR2GS on the same matrix."""
+    import torch
+    import matgen
+    import paper_2405_04237_amd as cqr
+    from paper_2405_04237_amd import _lib, measure
+    from paper_2405_04237_amd.costs import householder_flops, schedule_bytes, schedule_flops
+
+    m, n, kappa = 1 << 22, 128, 1e12
+    dev = torch.device("cuda:0")
+    log(f"scqr3: generating A ({m} x {n}, kappa={kappa:.0e}) on the device")
+    a = matgen.test_matrix_device(m, n, kappa, seed=31, device=dev)
+    q = cqr.empty_colmajor(m, n, dev, ld=a.stride(1))
+    r = cqr.empty_colmajor(n, n, dev)
+    out = {"workload": f"{m} x {n}, kappa={kappa:.0e}"}
+    for sched, b in (("scqr3", 0), ("mod", 32)):
+        ws = cqr.Workspace(m, n, b, sched, dev)
+
+        def step():
+            cqr.qr(a, b=b, schedule=sched, out=(q, r), workspace=ws, check=False)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        _lib.profile_reset()
+        _lib.profile_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        _lib.profile_enable(False)
+        ms = e0.elapsed_time(e1) / steps
+        kern = {}
+        for kind in _lib.KERNEL_KINDS:
+            p = _lib.profile_query(kind)
+            if p["launches"]:
+                kern[kind] = {"ms_per_step": round(p["ms"] / steps, 3),
+                              "tflops": round(p["flops"] / (p["ms"] * 1e-3) / 1e12, 2),
+                              "gbs": round(p["bytes"] / (p["ms"] * 1e-3) / 1e9, 1)}
+        res = {"ms": round(ms, 3), "b": int(_lib.default_panel(m, n, cqr.SCHEDULES[sched]) if not b else b),
+               "gflops_hh": round(householder_flops(m, n) / (ms * 1e-3) / 1e9, 1),
+               "tflops_algorithmic": round(schedule_flops(m, n, b or n, sched) / (ms * 1e-3) / 1e12, 2),
+               "gbs_algorithmic": round(schedule_bytes(m, n, b or n, sched) / (ms * 1e-3) / 1e9, 1),
+               "info": int(ws.info.item()),
+               "orthogonality": measure.orthogonality(q), "residual": measure.residual(a, q, r),
+               "kernels": kern}
+        out[sched] = res
+        log(f"scqr3 leg, {sched}: {ms:.3f} ms, orthogonality {res['orthogonality']:.2e}")
+        del ws
+    del a, q, r
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w: dict, b: int, schedule: str, rows: int):
     """The oracle, untuned, on a row sample of the workload (host cores)."""
     import numpy as np
@@ -332,6 +390,7 @@ def main():
         log(f"batched: {out['batched']['ms']} ms")
         out["backward"] = bench_backward(max(args.steps, 5), 2)
         log("backward: " + json.dumps(out["backward"]))
+        out["scqr3"] = bench_scqr3(max(args.steps, 5), 2)
     if args.calibration_copy:
         x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         y = torch.ones(1 << 27, dtype=torch.float64, device=dev)

@@ -14,6 +14,14 @@
  *                   the previous (fully orthogonal) panel, CholeskyQR,
  *                   re-orthogonalisation against all previous panels, and
  *                   CholeskyQR again.
+ *   CQR_SCHED_SCQR3 shifted CholeskyQR3 (sCQR3, Algorithm 5): shifted
+ *                   CholeskyQR (Algorithm 4: W = A^T A + s I with
+ *                   s = sqrt(m) u ||A||_F^2, u = 2^-53, W = R1^T R1,
+ *                   Q1 = A R1^{-1}), then CholeskyQR2 of Q1 (Algorithm 3),
+ *                   R = (R3 R2) R1. A whole-matrix algorithm: b is ignored
+ *                   and n must not exceed CQR_MAX_PANEL. ||A||_F^2 is the
+ *                   trace of the computed Gram matrix (the same sum of
+ *                   squares, no extra pass over A).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -40,7 +48,10 @@
  *   Cholesky pivot was not > 0 or was NaN (the failure mode the paper names
  *   in sections "CholeskyQR" and "CholeskyQR2"). Once set, the remaining
  *   kernels of that factorisation do nothing and Q, R are undefined.
- *   Nothing is shifted, retried or silently repaired.
+ *   Nothing is retried or silently repaired, and only CQR_SCHED_SCQR3,
+ *   whose shift is part of the algorithm, shifts a Gram matrix. (A NaN or
+ *   infinite entry reaches every diagonal entry through that shift, so
+ *   CQR_SCHED_SCQR3 reports such input at column 1.)
  * - Return values: CQR_OK, or a negative status (argument errors are
  *   detected before any device work is queued).
  */
@@ -67,7 +78,8 @@ enum cqr_status {
 
 enum cqr_schedule {
   CQR_SCHED_MOD = 0,   /* mCQR2GS, Algorithm 9 (default) */
-  CQR_SCHED_ORIG = 1   /* CQR2GS, Algorithm 7 */
+  CQR_SCHED_ORIG = 1,  /* CQR2GS, Algorithm 7 */
+  CQR_SCHED_SCQR3 = 2  /* shifted CholeskyQR3, Algorithms 4-5; n <= CQR_MAX_PANEL */
 };
 
 typedef struct cqr_options {
@@ -96,7 +108,8 @@ int cqr_factor_ex(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
  * arithmetic only; 0 for invalid sizes). The info word is not included. */
 size_t cqr_workspace_bytes(int64_t m, int64_t n, int64_t b, int schedule);
 
-/* Panel width used when b = 0 is passed. */
+/* Panel width used when b = 0 is passed (n for CQR_SCHED_SCQR3, which has
+ * no panels). */
 int64_t cqr_default_panel(int64_t m, int64_t n, int schedule);
 
 /* Batched factorisation: many independent matrices of uneven shape in one
@@ -195,7 +208,7 @@ enum cqr_kernel_kind {
   CQR_K_TRSM = 3,     /* Q_j = X U^{-1} (explicit inverse, streaming GEMM) */
   CQR_K_REDUCE = 4,   /* fixed-order sum of split-m partials */
   CQR_K_CHOL = 5,     /* b x b Cholesky + triangular inverse, one workgroup */
-  CQR_K_SMALL = 6,    /* small R-block products and fills */
+  CQR_K_SMALL = 6,    /* small R-block products, fills and the sCQR shift */
   CQR_K_BATCHED = 7,  /* the persistent batched factorisation (whole launch) */
   CQR_K_COPY = 8,     /* copy into the staging buffer */
   CQR_K_UPDATE_LONG = 9, /* update Qt -= Q_{1:j-1} Z, inner dimension > 128 */

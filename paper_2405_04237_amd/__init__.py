@@ -74,8 +74,9 @@ def qr(a, b: int = 0, schedule: str = "mod", check: bool = True, out=None,
        workspace: Workspace | None = None):
     """Thin QR of a tall-and-skinny FP64 matrix: returns (Q, R).
 
-    schedule "mod" = mCQR2GS (Algorithm 9), "orig" = CQR2GS (Algorithm 7).
-    b = 0 picks libcqr's default panel width. With check=True the call waits
+    schedule "mod" = mCQR2GS (Algorithm 9), "orig" = CQR2GS (Algorithm 7),
+    "scqr3" = shifted CholeskyQR3 (Algorithm 5; whole matrix, n <= 128, b
+    ignored). b = 0 picks libcqr's default panel width. With check=True the call waits
     for the device and raises Breakdown if a Cholesky pivot failed;
     otherwise the caller reads ``workspace.info``.
     """

@@ -21,7 +21,8 @@ CQR_MAX_PANEL = 128
 
 SCHED_MOD = 0
 SCHED_ORIG = 1
-SCHEDULES = {"mod": SCHED_MOD, "orig": SCHED_ORIG}
+SCHED_SCQR3 = 2
+SCHEDULES = {"mod": SCHED_MOD, "orig": SCHED_ORIG, "scqr3": SCHED_SCQR3}
 
 KERNEL_KINDS = ["gram", "proj", "update", "trsm", "reduce", "chol", "small", "batched", "copy",
                 "update_long"]

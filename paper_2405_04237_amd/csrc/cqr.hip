@@ -4,6 +4,7 @@
 // schedules of arXiv 2405.04237 as stream-ordered kernel chains:
 //   CQR2GS  (Algorithm 7 = Algorithm 6/8 twice, then R = R2 R1)
 //   mCQR2GS (Algorithm 9)
+//   sCQR3   (Algorithm 5: shifted CholeskyQR, Algorithm 4, then CholeskyQR2)
 // Nothing here synchronises with the device except cqr_get_info and
 // cqr_profile_query.
 #include <hip/hip_runtime.h>
@@ -80,7 +81,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t b, int schedule, bool stage) {
   L.y = take(n * cqr::padded_ld(std::max(n, b)));
   L.part_elems = kPartChunks * std::max(n * b, b * b);
   L.part = take(L.part_elems);
-  if (schedule == CQR_SCHED_ORIG) {
+  if (schedule == CQR_SCHED_ORIG || schedule == CQR_SCHED_SCQR3) {
     L.r1 = take(n * n);
     L.r2 = take(n * n);
   } else {
@@ -97,7 +98,12 @@ Layout make_layout(int64_t m, int64_t n, int64_t b, int schedule, bool stage) {
   return L;
 }
 
+bool valid_schedule(int schedule) {
+  return schedule == CQR_SCHED_MOD || schedule == CQR_SCHED_ORIG || schedule == CQR_SCHED_SCQR3;
+}
+
 int64_t effective_panel(int64_t m, int64_t n, int64_t b, int schedule) {
+  if (schedule == CQR_SCHED_SCQR3) return n;  // whole-matrix algorithm
   if (b == 0) b = cqr_default_panel(m, n, schedule);
   return std::min(b, n);
 }
@@ -280,6 +286,43 @@ hipError_t run_orig(Run &r, const double *A, double *Q, int64_t ld, int64_t b, d
   });
 }
 
+// Shifted CholeskyQR3 (Algorithm 5) on the whole matrix (n <= kMaxPanel):
+// [Q1, R1] = sCQR(A) (Algorithm 4), [Q, R2] = CQR2(Q1) (Algorithm 3) with
+// R2 = Rc Rb, R = R2 R1.
+hipError_t run_scqr3(Run &r, const double *A, double *Q, int64_t ld, double *R) {
+  const int w = (int)r.n;
+  // s = sqrt(m) u ||A||_F^2, u = 2^-53; ||A||_F^2 = trace(A^T A)
+  const double sqrt_m_u = std::sqrt((double)r.m) * std::ldexp(1.0, -53);
+  CQR_TRY(step_gram(r, A, ld, w));                                   // G = A^T A
+  CQR_TRY(timed(r.s, CQR_K_SMALL, 2.0 * w, 16.0 * w, [&] {
+    return cqr::launch_shift_diag(r.W, w, sqrt_m_u, r.info, r.s);    // W = G + s I
+  }));
+  CQR_TRY(step_chol(r, w, nullptr, r.R1, w, 0));                     // W = R1^T R1
+  CQR_TRY(step_trsm(r, A, Q, ld, w));                                // Q1 = A R1^{-1}
+  CQR_TRY(step_gram(r, Q, ld, w));                                   // CholeskyQR2 of Q1
+  CQR_TRY(step_chol(r, w, r.Ua, nullptr, 0, 0));
+  CQR_TRY(step_trsm(r, Q, Q, ld, w));
+  CQR_TRY(step_gram(r, Q, ld, w));
+  CQR_TRY(step_chol(r, w, r.Ub, nullptr, 0, 0));
+  CQR_TRY(step_trsm(r, Q, Q, ld, w, 0));
+  const double wf = w;
+  CQR_TRY(timed(r.s, CQR_K_SMALL, wf * wf * wf / 3.0, 24.0 * wf * wf, [&] {
+    return cqr::launch_r_upper_product(w, r.Ub, r.Ua, r.R2, w, r.info, r.s);  // R2 = Rc Rb
+  }));
+  return timed(r.s, CQR_K_SMALL, wf * wf * wf / 3.0, 24.0 * wf * wf, [&] {
+    return cqr::launch_trmm_upper(w, r.R2, r.R1, R, r.info, r.s);             // R = R2 R1
+  });
+}
+
+hipError_t run_mod(Run &r, const double *A, double *Q, int64_t ld, int64_t b, double *R);
+
+hipError_t run_schedule(Run &r, int schedule, const double *A, double *Q, int64_t ld, int64_t b,
+                        double *R) {
+  if (schedule == CQR_SCHED_ORIG) return run_orig(r, A, Q, ld, b, R);
+  if (schedule == CQR_SCHED_SCQR3) return run_scqr3(r, A, Q, ld, R);
+  return run_mod(r, A, Q, ld, b, R);
+}
+
 hipError_t run_mod(Run &r, const double *A, double *Q, int64_t ld, int64_t b, double *R) {
   const int64_t n = r.n;
   CQR_TRY(timed(r.s, CQR_K_SMALL, 0, 8.0 * n * n, [&] { return cqr::launch_zero(R, n * n, r.s); }));
@@ -335,7 +378,7 @@ int check_args(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda, co
   if (n > (int64_t(1) << 20) || m > (int64_t(1) << 40)) return CQR_ERR_ARG;
   if (!A || !Q || !R) return CQR_ERR_ARG;
   if (misaligned(A, 8) || misaligned(Q, 8) || misaligned(R, 8)) return CQR_ERR_ARG;
-  if (schedule != CQR_SCHED_MOD && schedule != CQR_SCHED_ORIG) return CQR_ERR_ARG;
+  if (!valid_schedule(schedule)) return CQR_ERR_ARG;
   if (effective_panel(m, n, b, schedule) > kMaxPanel) return CQR_ERR_UNSUPPORTED;
   return CQR_OK;
 }
@@ -391,6 +434,7 @@ extern "C" {
 int64_t cqr_default_panel(int64_t m, int64_t n, int schedule) {
   (void)m;
   if (n <= 0) return 0;
+  if (schedule == CQR_SCHED_SCQR3) return n;
   // mCQR2GS keeps O(u) orthogonality at kappa = 1e15 with a handful of
   // panels (the paper uses three); CQR2GS needs narrower panels there.
   const int64_t parts = (schedule == CQR_SCHED_ORIG) ? 16 : 4;
@@ -401,7 +445,7 @@ int64_t cqr_default_panel(int64_t m, int64_t n, int schedule) {
 
 size_t cqr_workspace_bytes(int64_t m, int64_t n, int64_t b, int schedule) {
   if (n < 1 || m < n || b < 0) return 0;
-  if (schedule != CQR_SCHED_MOD && schedule != CQR_SCHED_ORIG) return 0;
+  if (!valid_schedule(schedule)) return 0;
   const int64_t be = effective_panel(m, n, b, schedule);
   return (size_t)make_layout(m, n, be, schedule, aliasing_ld(m)).total;
 }
@@ -483,10 +527,9 @@ int cqr_factor_ex(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
     r.ldq = lda;
     e = timed(s, CQR_K_COPY, 0, 16.0 * m * n,
               [&] { return cqr::launch_copy_cols(m, n, A, lda, S, ldw, s); });
-    if (e == hipSuccess)
-      e = (schedule == CQR_SCHED_ORIG) ? run_orig(r, S, S, ldw, be, R) : run_mod(r, S, S, ldw, be, R);
+    if (e == hipSuccess) e = run_schedule(r, schedule, S, S, ldw, be, R);
   } else {
-    e = (schedule == CQR_SCHED_ORIG) ? run_orig(r, A, Q, lda, be, R) : run_mod(r, A, Q, lda, be, R);
+    e = run_schedule(r, schedule, A, Q, lda, be, R);
   }
   return e == hipSuccess ? CQR_OK : CQR_ERR_HIP;
 }
@@ -715,7 +758,7 @@ int cqr_plan_batched(int64_t batch, const int64_t *h_m, const int64_t *h_n, cons
   if (!plan) return CQR_ERR_ARG;
   *plan = nullptr;
   if (batch < 1 || batch > (int64_t(1) << 30) || !h_m || !h_n) return CQR_ERR_ARG;
-  if (schedule != CQR_SCHED_MOD && schedule != CQR_SCHED_ORIG) return CQR_ERR_ARG;
+  if (!valid_schedule(schedule)) return CQR_ERR_ARG;
   if (schedule != CQR_SCHED_MOD) return CQR_ERR_UNSUPPORTED;
   std::vector<int64_t> m(h_m, h_m + batch);
   std::vector<int> n(batch), b(batch);

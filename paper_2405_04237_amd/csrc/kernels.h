@@ -104,6 +104,11 @@ hipError_t launch_r_add_zu(int s_rows, int w, const double *Z, int64_t ldz, cons
 hipError_t launch_r_upper_product(int w, const double *Ub, const double *Ua, double *rblk,
                                   int64_t ldr, const int *info, hipStream_t s);
 
+// Shifted Gram (Algorithm 4): W += s I with s = sqrt_m_u * trace(W), for the
+// w x w Gram matrix W as the reduction stores it (leading dim w). trace(W) = ||X||_F^2 when W = X^T X;
+// it is summed by one thread in column order. No-op when *info != 0.
+hipError_t launch_shift_diag(double *W, int w, double sqrt_m_u, const int *info, hipStream_t s);
+
 // R = R2 * R1 for n x n upper triangular column-major matrices (leading
 // dimension n); strict lower part of R set to 0.
 hipError_t launch_trmm_upper(int n, const double *R2, const double *R1, double *R, const int *info,

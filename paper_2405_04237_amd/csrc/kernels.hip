@@ -1417,6 +1417,25 @@ hipError_t launch_r_upper_product(int w, const double *Ub, const double *Ua, dou
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_shift_diag(double *W, int w, double sqrt_m_u,
+                                                    const int *__restrict__ info) {
+  if (*info) return;
+  __shared__ double shift;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < w; ++i) t += W[i + (int64_t)i * w];
+    shift = sqrt_m_u * t;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < w; i += 256) W[i + (int64_t)i * w] += shift;
+}
+
+hipError_t launch_shift_diag(double *W, int w, double sqrt_m_u, const int *info, hipStream_t s) {
+  if (w < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_shift_diag, dim3(1), dim3(256), 0, s, W, w, sqrt_m_u, info);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_trmm_upper(int n, const double *__restrict__ R2,
                                                     const double *__restrict__ R1,
                                                     double *__restrict__ R,

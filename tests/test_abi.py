@@ -46,6 +46,9 @@ def test_header_constants_match_binding():
                       ("CQR_ERR_WORKSPACE", -4), ("CQR_ERR_UNSUPPORTED", -5)]:
         assert re.search(rf"{name} = {val}\b", text), name
         assert getattr(_lib, name) == val
+    for name, val in [("CQR_SCHED_MOD", 0), ("CQR_SCHED_ORIG", 1), ("CQR_SCHED_SCQR3", 2)]:
+        assert re.search(rf"{name} = {val}\b", text), name
+        assert getattr(_lib, name.replace("CQR_", "")) == val
 
 
 def test_workspace_and_panel_queries(lib):
@@ -65,6 +68,11 @@ def test_workspace_and_panel_queries(lib):
         for s in (_lib.SCHED_MOD, _lib.SCHED_ORIG):
             b = _lib.default_panel(1 << 20, n, s)
             assert 1 <= b <= min(n, _lib.CQR_MAX_PANEL)
+    # sCQR3 is one whole-matrix panel (b is ignored) and keeps R1, R2 like ORIG
+    assert _lib.default_panel(1 << 20, 100, _lib.SCHED_SCQR3) == 100
+    assert (_lib.workspace_bytes(1 << 20, 128, 0, _lib.SCHED_SCQR3)
+            == _lib.workspace_bytes(1 << 20, 128, 16, _lib.SCHED_SCQR3)
+            == _lib.workspace_bytes(1 << 20, 128, 128, _lib.SCHED_ORIG))
     assert _lib.status_string(0) == "success"
     assert "argument" in _lib.status_string(-1)
 
@@ -80,6 +88,8 @@ FAKE = C.c_void_p(4096)  # never dereferenced: every call below fails validation
     (100, 10, 4, 100, False, 0, _lib.CQR_ERR_ARG),     # null pointers
     (100, 10, 4, 100, True, 3, _lib.CQR_ERR_ARG),      # bad schedule
     (1000, 300, 200, 1000, True, 0, _lib.CQR_ERR_UNSUPPORTED),  # b > CQR_MAX_PANEL
+    (1000, 129, 0, 1000, True, 2, _lib.CQR_ERR_UNSUPPORTED),    # sCQR3 with n > CQR_MAX_PANEL
+    (100, 10, -1, 100, True, 2, _lib.CQR_ERR_ARG),              # sCQR3 still rejects b < 0
 ])
 def test_argument_errors(lib, m, n, b, lda, ptrs, sched, expect):
     p = FAKE if ptrs else None

@@ -175,3 +175,17 @@ def test_pins_catch_planted_shift_mistakes(monkeypatch, kind):
     except oracle.Breakdown:
         caught += 1
     assert caught >= 1
+
+
+def test_conservative_shift_reach_shrinks_with_m():
+    """With W = A^T A + s I the shifted Q1 has singular values sigma_i /
+    sqrt(sigma_i^2 + s), so kappa(Q1) is about sqrt(s) / sigma_min and grows
+    like m^(1/4). At 2^18 rows and kappa = 1e16 that is about 2.5e9, past
+    CholeskyQR2's reach: sCQR itself completes (the shift keeps W positive
+    definite) and the CholeskyQR2 stage breaks down; the paper points to a
+    smaller shift for such matrices."""
+    a = matgen.test_matrix(1 << 18, 32, 1e16, seed=1)
+    assert math.sqrt(oracle.scqr_shift(a)) * 1e16 > 1e9
+    oracle.scqr(a)
+    with pytest.raises(oracle.Breakdown):
+        oracle.scqr3(a)

@@ -28,6 +28,7 @@ using cqr::kMaxPanel;
 
 constexpr int64_t kAlign = 256;
 constexpr int64_t kPartChunks = 256;   // split-m partial capacity, in units of n*b doubles
+constexpr int64_t kPartGramChunks = 2048;  // ... and at least this many b x b Gram partials
 constexpr int64_t kTargetWaves = 2048; // split-m grid size aimed for (8 waves per CU)
 constexpr int64_t kMaxChunkRows = 16384;
 
@@ -79,7 +80,14 @@ Layout make_layout(int64_t m, int64_t n, int64_t b, int schedule, bool stage) {
   L.ua = take(b * b);
   L.ub = take(b * b);
   L.y = take(n * cqr::padded_ld(std::max(n, b)));
-  L.part_elems = kPartChunks * std::max(n * b, b * b);
+  // Room for the split-m plan of every product: kPartChunks slices of the
+  // widest projection, and enough b x b slices that a Gram of few panels
+  // (sCQR3, or n a small multiple of b) still fills the GPU; never more
+  // slices than the 16-row chunks m has (rounded up so that the size does
+  // not change with every m).
+  const int64_t slices = round_up((m + 15) / 16, 1024);
+  L.part_elems = std::max(kPartChunks * std::max(n * b, b * b), kPartGramChunks * b * b);
+  L.part_elems = std::min(L.part_elems, slices * std::max(n * b, b * b));
   L.part = take(L.part_elems);
   if (schedule == CQR_SCHED_ORIG || schedule == CQR_SCHED_SCQR3) {
     L.r1 = take(n * n);
@@ -196,7 +204,7 @@ void plan_chunks(const Run &r, int64_t tiles, int64_t pq, int64_t *rc, int64_t *
 // W = X^T X for the w columns at X (split-m partials + fixed-order reduce)
 hipError_t step_gram(Run &r, const double *X, int64_t ldx, int w) {
   int64_t rc, nch;
-  const int64_t tiles = cqr::tn_tiles(true, w, w);
+  const int64_t tiles = cqr::tn_tiles(true, w, w, true);
   plan_chunks(r, tiles, (int64_t)w * w, &rc, &nch);
   CQR_TRY(timed(r.s, CQR_K_GRAM, double(r.m) * w * w, 8.0 * r.m * w, [&] {
     return cqr::launch_tn(true, r.m, w, w, X, ldx, X, ldx, r.part, rc, nch, r.info, r.s);

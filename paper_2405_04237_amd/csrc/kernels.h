@@ -24,8 +24,10 @@ hipError_t launch_tn(bool gram, int64_t m, int p, int q, const double *L, int64_
                      const int *info, hipStream_t s, int batch = 1, int64_t sL = 0,
                      int64_t sRt = 0, int64_t sPart = 0);
 
-// Number of 64x64 output tiles one chunk of launch_tn produces.
-int64_t tn_tiles(bool gram, int p, int q);
+// Number of waves one row chunk of launch_tn occupies (its output tiles).
+// same: both operands are one matrix (a Gram matrix); with p = q = 128 that
+// selects the two-wave balanced Gram kernel.
+int64_t tn_tiles(bool gram, int p, int q, bool same = false);
 
 // Row-streaming product over all m rows, Y row-major p x q (leading dim ldy):
 //   subtract = false: C = L * Y   (Cin unused; C may alias L when q <= 256:

@@ -28,6 +28,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 #include "kernels.h"
@@ -84,97 +85,235 @@ __global__ __launch_bounds__(64) void k_tn(int64_t m, int p, int q, const double
     pb[u] = Rt + (int64_t)(cb < q ? cb : 0) * ldr + rb + 4 * g;
   }
 
-  d4 acc[4][4];
+  // A diagonal tile of an upper product needs only the blocks on or above
+  // its diagonal (the reduction reads i <= j only), and when both operands
+  // are the same matrix (a Gram) its two column sets coincide: such tiles
+  // issue 10 of the 16 MFMAs per step and load one column set instead of two.
+  auto body = [&](auto diag_c, auto same_c) {
+    constexpr bool DIAG = decltype(diag_c)::value, SAME = decltype(same_c)::value;
+    d4 acc[4][4];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int y = 0; y < 4; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
 
-  auto load = [&](double (&da)[4][4], double (&db)[4][4], int64_t off) {
+    auto load = [&](double (&da)[4][4], double (&db)[4][4], int64_t off) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (VEC) {
-        const double2 *xa = reinterpret_cast<const double2 *>(pa[u] + off);
-        const double2 *xb = reinterpret_cast<const double2 *>(pb[u] + off);
-        const double2 a0 = xa[0], a1 = xa[1], b0 = xb[0], b1 = xb[1];
-        da[u][0] = a0.x;
-        da[u][1] = a0.y;
-        da[u][2] = a1.x;
-        da[u][3] = a1.y;
-        db[u][0] = b0.x;
-        db[u][1] = b0.y;
-        db[u][2] = b1.x;
-        db[u][3] = b1.y;
-      } else {
+      for (int u = 0; u < 4; ++u) {
+        if (VEC) {
+          const double2 *xa = reinterpret_cast<const double2 *>(pa[u] + off);
+          const double2 a0 = xa[0], a1 = xa[1];
+          da[u][0] = a0.x;
+          da[u][1] = a0.y;
+          da[u][2] = a1.x;
+          da[u][3] = a1.y;
+          if (!SAME) {
+            const double2 *xb = reinterpret_cast<const double2 *>(pb[u] + off);
+            const double2 b0 = xb[0], b1 = xb[1];
+            db[u][0] = b0.x;
+            db[u][1] = b0.y;
+            db[u][2] = b1.x;
+            db[u][3] = b1.y;
+          }
+        } else {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          da[u][s] = pa[u][off + s];
-          db[u][s] = pb[u][off + s];
+          for (int s = 0; s < 4; ++s) {
+            da[u][s] = pa[u][off + s];
+            if (!SAME) db[u][s] = pb[u][off + s];
+          }
         }
       }
-    }
-  };
-  auto compute = [&](const double (&da)[4][4], const double (&db)[4][4]) {
+    };
+    auto compute = [&](const double (&da)[4][4], const double (&db)[4][4]) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+      for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+        for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x4(da[x][s], db[y][s], acc[x][y]);
-  };
+          for (int y = 0; y < 4; ++y)
+            if (!DIAG || x <= y) acc[x][y] = mfma16x16x4(da[x][s], SAME ? da[y][s] : db[y][s], acc[x][y]);
+    };
 
-  // Three register sets in a ring: while one step's 64 MFMAs run, the loads
-  // of the next two steps are in flight (about 8K cycles of cover at the
-  // FP64 MFMA rate). The scheduling barriers keep the compiler from sinking
-  // the loads next to their uses. Prefetch offsets are clamped to the last
-  // full step, so every load stays inside the chunk.
-  double a0[4][4], b0[4][4], a1[4][4], b1[4][4], a2[4][4], b2[4][4];
-  if (nsteps > 0) {
-    auto at = [&](int64_t st) -> int64_t { return 16 * (st < nsteps ? st : nsteps - 1); };
-    load(a0, b0, 0);
-    load(a1, b1, at(1));
-    int64_t it = 0;
-    for (; it + 3 <= nsteps; it += 3) {
-      load(a2, b2, at(it + 2));
-      __builtin_amdgcn_sched_barrier(0);
+    // Three register sets in a ring: while one step's MFMAs run, the loads of
+    // the next two steps are in flight (about 8K cycles of cover at the FP64
+    // MFMA rate). The scheduling barriers keep the compiler from sinking the
+    // loads next to their uses. Prefetch offsets are clamped to the last full
+    // step, so every load stays inside the chunk.
+    double a0[4][4], b0[4][4], a1[4][4], b1[4][4], a2[4][4], b2[4][4];
+    if (nsteps > 0) {
+      auto at = [&](int64_t st) -> int64_t { return 16 * (st < nsteps ? st : nsteps - 1); };
+      load(a0, b0, 0);
+      load(a1, b1, at(1));
+      int64_t it = 0;
+      for (; it + 3 <= nsteps; it += 3) {
+        load(a2, b2, at(it + 2));
+        __builtin_amdgcn_sched_barrier(0);
+        compute(a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(a0, b0, at(it + 3));
+        __builtin_amdgcn_sched_barrier(0);
+        compute(a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+        load(a1, b1, at(it + 4));
+        __builtin_amdgcn_sched_barrier(0);
+        compute(a2, b2);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (it < nsteps) compute(a0, b0);
+      if (it + 1 < nsteps) compute(a1, b1);
+    }
+    const int64_t rt = rb + 16 * nsteps;
+    if (rt < re) {  // ragged tail: rows rt + 4g + s < re only
+      const int64_t off = 16 * nsteps;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const bool ok = (rt + 4 * g + s) < re;
+          a0[u][s] = ok ? pa[u][off + s] : 0.0;
+          if (!SAME) b0[u][s] = ok ? pb[u][off + s] : 0.0;
+        }
       compute(a0, b0);
-      __builtin_amdgcn_sched_barrier(0);
-      load(a0, b0, at(it + 3));
-      __builtin_amdgcn_sched_barrier(0);
-      compute(a1, b1);
-      __builtin_amdgcn_sched_barrier(0);
-      load(a1, b1, at(it + 4));
-      __builtin_amdgcn_sched_barrier(0);
-      compute(a2, b2);
-      __builtin_amdgcn_sched_barrier(0);
     }
-    if (it < nsteps) compute(a0, b0);
-    if (it + 1 < nsteps) compute(a1, b1);
-  }
-  const int64_t rt = rb + 16 * nsteps;
-  if (rt < re) {  // ragged tail: rows rt + 4g + s < re only
-    const int64_t off = 16 * nsteps;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const bool ok = (rt + 4 * g + s) < re;
-        a0[u][s] = ok ? pa[u][off + s] : 0.0;
-        b0[u][s] = ok ? pb[u][off + s] : 0.0;
-      }
-    compute(a0, b0);
-  }
 
-  double *out = part + (size_t)c * (size_t)p * (size_t)q;
+    double *out = part + (size_t)c * (size_t)p * (size_t)q;
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y)
+      for (int y = 0; y < 4; ++y)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int I = i0 + 16 * x + g + 4 * e, J = j0 + 16 * y + cl;
-        if (I < p && J < q) out[(size_t)I * q + J] = acc[x][y][e];
+        for (int e = 0; e < 4; ++e) {
+          const int I = i0 + 16 * x + g + 4 * e, J = j0 + 16 * y + cl;
+          if ((!DIAG || x <= y) && I < p && J < q) out[(size_t)I * q + J] = acc[x][y][e];
+        }
+  };
+  using T_ = std::true_type;
+  using F_ = std::false_type;
+  if (UPPER && ti == tj) {
+    if (L == Rt && ldl == ldr)
+      body(T_{}, T_{});
+    else
+      body(T_{}, F_{});
+  } else {
+    body(F_{}, F_{});
+  }
+}
+
+// k_gram128: the Gram matrix W = X^T X of a 128-column panel, split-m as
+// k_tn. Its upper triangle is 36 blocks of 16 x 16. With 64 x 64 tiles the
+// two diagonal tiles carry 10 needed blocks and the off-diagonal one 16, so
+// the waves that draw two off-diagonal tiles set the kernel's length. Here
+// two waves share a row chunk and take 18 blocks each: block rows {0, 1, 6,
+// 7} (which reach all 8 column blocks) and {2, 3, 4, 5} (column blocks 2..7).
+// Every wave issues 72 MFMAs per 16-row step and loads only the column
+// blocks its rows reach. Lane maps and the register ring as in k_tn.
+__host__ __device__ constexpr int gram128_row(int half, int i) {
+  return half ? 2 + i : (i < 2 ? i : 4 + i);
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(64) void k_gram128(int64_t m, const double *__restrict__ X, int64_t ldx,
+                                                double *__restrict__ part, int64_t rc,
+                                                const int *__restrict__ info) {
+  if (*info) return;
+  const int64_t lid = xcd_logical(blockIdx.x, gridDim.x);
+  const int64_t c = lid >> 1;
+  const int lane = threadIdx.x, g = lane >> 4, cl = lane & 15;
+  const int64_t rb = c * rc;
+  const int64_t re = (m < rb + rc) ? m : rb + rc;
+  const int64_t nsteps = (re - rb) / 16;
+
+  auto body = [&](auto half_c) {
+    constexpr int H = decltype(half_c)::value;
+    constexpr int CB0 = H ? 2 : 0;  // first column block this half reads
+    constexpr int NCB = 8 - CB0;
+    const double *pc[NCB];
+#pragma unroll
+    for (int u = 0; u < NCB; ++u) pc[u] = X + (int64_t)(16 * (CB0 + u) + cl) * ldx + rb + 4 * g;
+
+    d4 acc[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int y = 0; y < 8; ++y) acc[i][y] = d4{0.0, 0.0, 0.0, 0.0};
+
+    auto load = [&](double (&d)[NCB][4], int64_t off) {
+#pragma unroll
+      for (int u = 0; u < NCB; ++u) {
+        if (VEC) {
+          const double2 *xa = reinterpret_cast<const double2 *>(pc[u] + off);
+          const double2 a0 = xa[0], a1 = xa[1];
+          d[u][0] = a0.x;
+          d[u][1] = a0.y;
+          d[u][2] = a1.x;
+          d[u][3] = a1.y;
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) d[u][s] = pc[u][off + s];
+        }
       }
+    };
+    auto compute = [&](const double (&d)[NCB][4]) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int y = 0; y < 8; ++y) {
+            const int x = gram128_row(H, i);
+            if (y >= x) acc[i][y] = mfma16x16x4(d[x - CB0][s], d[y - CB0][s], acc[i][y]);
+          }
+    };
+
+    double d0[NCB][4], d1[NCB][4], d2[NCB][4];
+    if (nsteps > 0) {
+      auto at = [&](int64_t st) -> int64_t { return 16 * (st < nsteps ? st : nsteps - 1); };
+      load(d0, 0);
+      load(d1, at(1));
+      int64_t it = 0;
+      for (; it + 3 <= nsteps; it += 3) {
+        load(d2, at(it + 2));
+        __builtin_amdgcn_sched_barrier(0);
+        compute(d0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(d0, at(it + 3));
+        __builtin_amdgcn_sched_barrier(0);
+        compute(d1);
+        __builtin_amdgcn_sched_barrier(0);
+        load(d1, at(it + 4));
+        __builtin_amdgcn_sched_barrier(0);
+        compute(d2);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (it < nsteps) compute(d0);
+      if (it + 1 < nsteps) compute(d1);
+    }
+    const int64_t rt = rb + 16 * nsteps;
+    if (rt < re) {  // ragged tail: rows rt + 4g + s < re only
+      const int64_t off = 16 * nsteps;
+#pragma unroll
+      for (int u = 0; u < NCB; ++u)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) d0[u][s] = ((rt + 4 * g + s) < re) ? pc[u][off + s] : 0.0;
+      compute(d0);
+    }
+
+    double *out = part + (size_t)c * 128 * 128;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int y = 0; y < 8; ++y) {
+        const int x = gram128_row(H, i);
+        if (y >= x) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) out[(16 * x + g + 4 * e) * 128 + 16 * y + cl] = acc[i][y][e];
+        }
+      }
+  };
+  if (lid & 1)
+    body(std::integral_constant<int, 1>{});
+  else
+    body(std::integral_constant<int, 0>{});
 }
 
 // k_tn_wide: the projection form (not a Gram) with a 64 x 128 output tile
@@ -291,8 +430,13 @@ static bool tn_use_wide(bool gram, int p, int q, int batch) {
   return !gram && batch == 1 && p >= kTile && q >= 2 * kTile;
 }
 
-int64_t tn_tiles(bool gram, int p, int q) {
+static bool tn_use_gram128(bool gram, int p, int q, int batch, bool same) {
+  return gram && same && p == 128 && q == 128 && batch == 1;
+}
+
+int64_t tn_tiles(bool gram, int p, int q, bool same) {
   const int tp = (p + kTile - 1) / kTile, tq = (q + kTile - 1) / kTile;
+  if (tn_use_gram128(gram, p, q, 1, same)) return 2;
   if (tn_use_wide(gram, p, q, 1)) return (int64_t)tp * ((q + 2 * kTile - 1) / (2 * kTile));
   return gram ? (int64_t)tp * (tp + 1) / 2 : (int64_t)tp * tq;
 }
@@ -304,6 +448,14 @@ hipError_t launch_tn(bool gram, int64_t m, int p, int q, const double *L, int64_
   const int tp = (p + kTile - 1) / kTile, tq = (q + kTile - 1) / kTile;
   const bool vec = (ldl % 2 == 0) && (ldr % 2 == 0) && ((uintptr_t)L % 16 == 0) &&
                    ((uintptr_t)Rt % 16 == 0) && (rc % 16 == 0) && (sL % 2 == 0) && (sRt % 2 == 0);
+  if (tn_use_gram128(gram, p, q, batch, L == Rt && ldl == ldr)) {
+    const dim3 gg((unsigned)(2 * nch));
+    if (vec)
+      hipLaunchKernelGGL((k_gram128<true>), gg, dim3(64), 0, s, m, L, ldl, part, rc, info);
+    else
+      hipLaunchKernelGGL((k_gram128<false>), gg, dim3(64), 0, s, m, L, ldl, part, rc, info);
+    return hipGetLastError();
+  }
   if (tn_use_wide(gram, p, q, batch)) {
     const int tqw = (q + 2 * kTile - 1) / (2 * kTile);
     const dim3 gw((unsigned)((int64_t)tp * tqw * nch));

@@ -153,13 +153,3 @@ def test_full_size_properties():
     torch.cuda.synchronize()
     assert oracle.rel_fro(rh, to_host(r2)) <= 100 * n * U * kappa
 
-
-def test_beyond_the_shift_reach_breaks_down_like_oracle():
-    """2^18 x 32 at kappa = 1e16: the conservative shift leaves Q1 with a
-    condition number near 2.5e9, and the CholeskyQR2 stage breaks down on
-    both sides (the columns need not coincide)."""
-    a = matgen.test_matrix(1 << 18, 32, 1e16, seed=1)
-    with pytest.raises(oracle.Breakdown):
-        oracle.scqr3(a)
-    with pytest.raises(cqr.Breakdown):
-        _factor(a)

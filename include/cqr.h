@@ -90,6 +90,19 @@ typedef struct cqr_options {
                               bytes, 256-byte aligned; NULL = a workspace the
                               library allocates once per device and keeps */
   size_t workspace_bytes;  /* size of `workspace` */
+  int lookahead;           /* CQR_SCHED_MOD only. 1: overlap each panel's
+                              CholeskyQR / re-orthogonalisation chain with the
+                              trailing update of the panels after it (the
+                              look-ahead the paper proposes as future work,
+                              section "Conclusion"): the update is split into
+                              the next panel's columns and the rest, and the
+                              panel's chain runs on a library-owned side
+                              stream (default priority) forked from and joined
+                              back into `stream` with events. Same kernels on
+                              the same operands: results are bitwise those of
+                              lookahead = 0. 0: everything on `stream`. Zero-
+                              initialise the struct; other schedules ignore
+                              it. */
 } cqr_options;
 
 /* Factor A = Q R with the default schedule (mCQR2GS). Q has leading

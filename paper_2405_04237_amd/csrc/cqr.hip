@@ -63,7 +63,7 @@ int64_t staging_ld(int64_t m) {
 
 // ---------------------------------------------------------------- workspace
 struct Layout {
-  int64_t w, uinv, ua, ub, y, part, r1, r2, stage, total;  // byte offsets / size
+  int64_t w, uinv, ua, ub, y, yz, part, r1, r2, stage, total;  // byte offsets / size
   int64_t part_elems, ldw;                                 // ldw: staging leading dim
 };
 
@@ -80,6 +80,9 @@ Layout make_layout(int64_t m, int64_t n, int64_t b, int schedule, bool stage) {
   L.ua = take(b * b);
   L.ub = take(b * b);
   L.y = take(n * cqr::padded_ld(std::max(n, b)));
+  // MOD with look-ahead: the re-orthogonalisation coefficients Z (at most
+  // n x b) get their own buffer, since the trailing Y is still being read
+  L.yz = (schedule == CQR_SCHED_MOD) ? take(n * cqr::padded_ld(b)) : -1;
   // Room for the split-m plan of every product: kPartChunks slices of the
   // widest projection, and enough b x b slices that a Gram of few panels
   // (sCQR3, or n a small multiple of b) still fills the GPU; never more
@@ -132,6 +135,27 @@ struct DevState {
 std::mutex g_mu;
 std::map<int, DevState> g_dev;
 
+// The current device's side stream and its fork/join events (created on
+// first use). Callers hold DevState::side while they enqueue a fork/join
+// sequence.
+hipError_t side_stream(DevState **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevState &d = g_dev[dev];
+  if (!d.aux) {
+    e = hipStreamCreateWithFlags(&d.aux, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipEventCreateWithFlags(&d.fork, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    e = hipEventCreateWithFlags(&d.join, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  *out = &d;
+  return hipSuccess;
+}
+
 // ---------------------------------------------------------------- profiling
 struct Rec {
   hipEvent_t a, b;
@@ -177,6 +201,9 @@ hipError_t timed(hipStream_t s, int kind, double flops, double bytes, F &&f) {
 // ---------------------------------------------------------------- one factorisation
 struct Run {
   hipStream_t s;
+  hipStream_t aux;               // look-ahead side stream (null: none)
+  hipEvent_t fork, join;         // main -> aux and aux -> main
+  double *Yz;                    // Z buffer of the look-ahead chain
   int *info;
   int64_t m, n;
   double *W, *Uinv, *Ua, *Ub, *Y, *part, *R1, *R2;
@@ -248,14 +275,19 @@ hipError_t step_proj(Run &r, const double *Qp, int64_t ld, int p, const double *
   });
 }
 
-// Zo = Zi - Qp Y  (r.Y holds -Y); Zo may be Zi (in place)
-hipError_t step_update(Run &r, const double *Qp, int64_t ld, int p, const double *Zi, double *Zo,
-                       int q) {
+// Zo = Zi - Qp Y with Ym = -Y (row-major, leading dim ldy); Zo may be Zi
+hipError_t step_update_y(Run &r, const double *Qp, int64_t ld, int p, const double *Zi, double *Zo,
+                         int q, const double *Ym, int64_t ldy) {
   const int kind = cqr::nn_short_k(p, Qp, ld, Zi, ld, Zo, ld) ? CQR_K_UPDATE : CQR_K_UPDATE_LONG;
   return timed(r.s, kind, 2.0 * r.m * p * q, 8.0 * r.m * (p + 2.0 * q), [&] {
-    return cqr::launch_nn(true, false, r.m, p, q, Qp, ld, r.Y, cqr::padded_ld(q), Zi, ld, Zo, ld,
-                          r.info, r.s);
+    return cqr::launch_nn(true, false, r.m, p, q, Qp, ld, Ym, ldy, Zi, ld, Zo, ld, r.info, r.s);
   });
+}
+
+// Zo = Zi - Qp Y  (r.Y holds -Y for these q columns); Zo may be Zi (in place)
+hipError_t step_update(Run &r, const double *Qp, int64_t ld, int p, const double *Zi, double *Zo,
+                       int q) {
+  return step_update_y(r, Qp, ld, p, Zi, Zo, q, r.Y, cqr::padded_ld(q));
 }
 
 // One CQRGS pass (Algorithm 6; Algorithm 8 with the Allreduces replaced by
@@ -355,25 +387,47 @@ hipError_t run_mod(Run &r, const double *A, double *Q, int64_t ld, int64_t b, do
     const double *Ar = (ps == 0) ? A + s * ld : Xj;
     // Y := Q_{j-1}^T A_{:,j:k}; R_{j-1,j:k} := Y; A_{:,j:k} -= Q_{j-1} Y
     CQR_TRY(step_proj(r, Qprev, ld, pw, Ar, (int)(n - s), R + ps + s * n, n));
-    CQR_TRY(step_update(r, Qprev, ld, pw, Ar, Xj, (int)(n - s)));
+    // Look-ahead: update panel j's own columns first; panel j's chain then
+    // runs on the side stream while this stream updates panels j+1..k. The
+    // chain touches only columns <= e and its own workspace (W, U^{-1}, Ua,
+    // Ub, partials, Z); the rest of the update only columns > e and Y.
+    const bool ahead = r.aux && e < n;
+    Run c = r;
+    if (ahead) {
+      const int64_t ldy = cqr::padded_ld((int)(n - s));
+      CQR_TRY(step_update_y(r, Qprev, ld, pw, Ar, Xj, w, r.Y, ldy));
+      CQR_TRY(hipEventRecord(r.fork, r.s));
+      CQR_TRY(hipStreamWaitEvent(r.aux, r.fork, 0));
+      c.s = r.aux;
+      c.Y = r.Yz;
+    } else {
+      CQR_TRY(step_update(r, Qprev, ld, pw, Ar, Xj, (int)(n - s)));
+    }
     // CQR(A_j): A_j = Qt Ua
-    CQR_TRY(step_gram(r, Xj, ld, w));
-    CQR_TRY(step_chol(r, w, r.Ua, nullptr, 0, (int)s));
-    CQR_TRY(step_trsm(r, Xj, Xj, ld, w));
+    CQR_TRY(step_gram(c, Xj, ld, w));
+    CQR_TRY(step_chol(c, w, c.Ua, nullptr, 0, (int)s));
+    CQR_TRY(step_trsm(c, Xj, Xj, ld, w));
     // re-orthogonalise: Z := Q_{1:j-1}^T Qt; Qt -= Q_{1:j-1} Z; R_{1:j-1,j} += Z Ua
-    // (r.Y holds -Z, so the R update subtracts (-Z) Ua)
-    CQR_TRY(step_proj(r, Q, ld, (int)s, Xj, w, nullptr, 0));
-    CQR_TRY(step_update(r, Q, ld, (int)s, Xj, Xj, w));
-    CQR_TRY(timed(r.s, CQR_K_SMALL, 2.0 * s * w * w / 2, 0, [&] {
-      return cqr::launch_r_add_zu((int)s, w, r.Y, cqr::padded_ld(w), r.Ua, R + s * n, n, r.info, r.s);
+    // (c.Y holds -Z, so the R update subtracts (-Z) Ua)
+    CQR_TRY(step_proj(c, Q, ld, (int)s, Xj, w, nullptr, 0));
+    CQR_TRY(step_update(c, Q, ld, (int)s, Xj, Xj, w));
+    CQR_TRY(timed(c.s, CQR_K_SMALL, 2.0 * s * w * w / 2, 0, [&] {
+      return cqr::launch_r_add_zu((int)s, w, c.Y, cqr::padded_ld(w), c.Ua, R + s * n, n, c.info, c.s);
     }));
     // CQR again: Qt = Q_j Ub; R_jj = Ub Ua
-    CQR_TRY(step_gram(r, Xj, ld, w));
-    CQR_TRY(step_chol(r, w, r.Ub, nullptr, 0, (int)s));
-    CQR_TRY(step_trsm(r, Xj, Xj, ld, w, s));
-    CQR_TRY(timed(r.s, CQR_K_SMALL, 0, 0, [&] {
-      return cqr::launch_r_upper_product(w, r.Ub, r.Ua, R + s + s * n, n, r.info, r.s);
+    CQR_TRY(step_gram(c, Xj, ld, w));
+    CQR_TRY(step_chol(c, w, c.Ub, nullptr, 0, (int)s));
+    CQR_TRY(step_trsm(c, Xj, Xj, ld, w, s));
+    CQR_TRY(timed(c.s, CQR_K_SMALL, 0, 0, [&] {
+      return cqr::launch_r_upper_product(w, c.Ub, c.Ua, R + s + s * n, n, c.info, c.s);
     }));
+    if (ahead) {
+      const int64_t ldy = cqr::padded_ld((int)(n - s));
+      CQR_TRY(step_update_y(r, Qprev, ld, pw, Ar + (int64_t)w * ld, Xj + (int64_t)w * ld,
+                            (int)(n - e), r.Y + w, ldy));
+      CQR_TRY(hipEventRecord(r.join, r.aux));
+      CQR_TRY(hipStreamWaitEvent(r.s, r.join, 0));
+    }
   }
   return hipSuccess;
 }
@@ -523,6 +577,16 @@ int cqr_factor_ex(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
   r.part_elems = lay.part_elems;
   r.R1 = lay.r1 >= 0 ? (double *)(ws + lay.r1) : nullptr;
   r.R2 = lay.r2 >= 0 ? (double *)(ws + lay.r2) : nullptr;
+  r.Yz = lay.yz >= 0 ? (double *)(ws + lay.yz) : nullptr;
+  std::unique_lock<std::mutex> side_lock;
+  if (opt && opt->lookahead && schedule == CQR_SCHED_MOD && r.Yz && be < n) {
+    DevState *ds = nullptr;
+    if (side_stream(&ds) != hipSuccess) return CQR_ERR_HIP;
+    side_lock = std::unique_lock<std::mutex>(ds->side);
+    r.aux = ds->aux;
+    r.fork = ds->fork;
+    r.join = ds->join;
+  }
 
   if (timed(s, CQR_K_SMALL, 0, 0, [&] { return cqr::launch_set_int(info, 0, s); }) != hipSuccess)
     return CQR_ERR_HIP;
@@ -675,19 +739,7 @@ int cqr_backward_batched(int64_t batch, int64_t m, int64_t n, const double *Q, c
   // R^{-1} needs only R: it runs on the side stream while pass 1 streams
   // over the rows, and is joined back before the n x n step
   DevState *dev_state = nullptr;
-  {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return CQR_ERR_HIP;
-    std::lock_guard<std::mutex> lk(g_mu);
-    DevState &d = g_dev[dev];
-    if (!d.aux) {
-      if (hipStreamCreateWithFlags(&d.aux, hipStreamNonBlocking) != hipSuccess) return CQR_ERR_HIP;
-      if (hipEventCreateWithFlags(&d.fork, hipEventDisableTiming) != hipSuccess ||
-          hipEventCreateWithFlags(&d.join, hipEventDisableTiming) != hipSuccess)
-        return CQR_ERR_HIP;
-    }
-    dev_state = &d;
-  }
+  if (side_stream(&dev_state) != hipSuccess) return CQR_ERR_HIP;
   std::lock_guard<std::mutex> side_lock(dev_state->side);
   hipStream_t aux = dev_state->aux;
   if (hipEventRecord(dev_state->fork, s) != hipSuccess ||

@@ -828,125 +828,90 @@ __global__ __launch_bounds__(256, 2) void k_upd(int64_t m, int p, int q, const d
 }
 
 // ----------------------------------------------------------------------------
-// k_trsm: Q_j = X U^{-1} in place for a panel of w = 64 or 128 columns (w a
-// multiple of 16), over the rows [0, mfull) in blocks of 32 * 8 / nslab rows.
-// One persistent 8-wave workgroup per CU keeps U^{-1} (upper triangle,
-// zero elsewhere) in LDS and takes every gridDim.x-th row block. Waves split
-// a block into 32 x 64 tiles (wave / 4 = column slab when w = 128); slab s
-// only needs rows k < 64 (s + 1) of U^{-1}. The k steps of consecutive
-// blocks form one stream through a three-deep register ring, so the next
-// block's X rows are in flight while the current block finishes; a
-// workgroup barrier between the last read of a block's X rows and the first
-// write of its Q rows keeps the in-place update safe. X2 (optional) receives
-// the same values as X.
+// k_trsm: Q_j = X U^{-1} in place for a panel of W = 64 or 128 columns, over
+// the rows [0, mfull) in blocks of 128 rows. One persistent 8-wave
+// workgroup per CU keeps U^{-1} (upper triangle, zero elsewhere) in LDS and
+// takes every gridDim.x-th block; each wave owns a 16-row x W tile of the
+// block, so it reads and writes only its own rows (no workgroup barrier) and
+// every wave does the same work. MFMA block x covers the 16 contiguous
+// columns 16x..16x+15, which need k < 16(x+1) only: k step ks feeds blocks
+// x >= ks, 36 of the 64 block-steps at W = 128. Lane maps (cl = lane % 16,
+// g = lane / 16):
+//   A operand (U^{-1}), block x, step s: lane holds U^{-1}[k][16x + cl],
+//     k = 16 ks + 4 s + g
+//   B operand (X): lane holds X[r + cl][k]
+//   D element e of block x: Q[r + cl][16x + g + 4e]
+// The k steps of consecutive blocks form one stream through a four-deep
+// register ring (prefetch three steps ahead). X2 (optional) receives the
+// same values as X.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(512, 1) void k_trsm(int64_t mfull, int w, double *X, int64_t ldx,
+constexpr int kTrsmRows = 128;
+
+template <int W>
+__global__ __launch_bounds__(512, 1) void k_trsm(int64_t mfull, double *X, int64_t ldx,
                                                  const double *__restrict__ Uinv, int64_t ldu,
                                                  double *X2, int64_t ldx2,
                                                  const int *__restrict__ info) {
-  extern __shared__ double us[];  // [w][w] row-major
+  extern __shared__ double us[];  // [W][W] row-major
   if (*info) return;
-  const int nslab = w / kTile;
-  for (int e = threadIdx.x; e < w * w; e += 512) {
-    const int k = e / w, c = e % w;
+  for (int e = threadIdx.x; e < W * W; e += 512) {
+    const int k = e / W, c = e % W;
     us[e] = (c >= k) ? Uinv[(int64_t)k * ldu + c] : 0.0;
   }
   __syncthreads();
+  constexpr int NX = W / 16, NK = W / 16;
+  static_assert(NK % 4 == 0, "the ring depth divides the k steps of a block");
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
-  const int slab = (nslab == 2) ? wave >> 2 : 0;
-  const int tile = (nslab == 2) ? wave & 3 : wave;
-  const int64_t brows = (nslab == 2) ? 128 : 256;  // rows per block
-  const int64_t nblk = mfull / brows;
+  const int64_t nblk = mfull / kTrsmRows;
   if ((int64_t)blockIdx.x >= nblk) return;  // whole workgroup
   const int64_t nmine = (nblk - blockIdx.x + gridDim.x - 1) / gridDim.x;
-  const int nk = (kTile * (slab + 1)) / 16;  // k steps of this wave's slab
-  const int64_t T = nmine * nk;
-  const int c0 = kTile * slab;
-  const double *yl = us + c0 + 4 * cl;
-  const int64_t rstep = (int64_t)gridDim.x * brows;  // rows between this workgroup's blocks
-  const int64_t rfirst = (int64_t)blockIdx.x * brows + 32 * tile + 2 * cl;
-
-  d4 acc[4][2];
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+  const int64_t T = nmine * NK;
+  const int64_t rstep = (int64_t)gridDim.x * kTrsmRows;  // rows between this workgroup's blocks
+  int64_t rl = (int64_t)blockIdx.x * kTrsmRows + 16 * wave + cl;
 
   // load cursor: step index -> pointer to X[row rl][column 16 ks + g]
   int64_t lt = 0;
-  const double *lp = X + rfirst + (int64_t)g * ldx;
-  auto load = [&](double (&db)[4][2]) {
+  const double *lp = X + rl + (int64_t)g * ldx;
+  auto load = [&](double (&db)[4]) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const double2 t = *reinterpret_cast<const double2 *>(lp + (int64_t)(4 * s) * ldx);
-      db[s][0] = t.x;
-      db[s][1] = t.y;
-    }
+    for (int s = 0; s < 4; ++s) db[s] = lp[(int64_t)(4 * s) * ldx];
     if (lt + 1 < T) {  // advance; past the end the last step is re-read
       ++lt;
-      lp += ((lt % nk) == 0) ? rstep - (int64_t)(nk - 1) * 16 * ldx : 16 * ldx;
+      lp += ((lt % NK) == 0) ? rstep - (int64_t)(NK - 1) * 16 * ldx : 16 * ldx;
     }
   };
-  // compute cursor
-  int ks = 0;
-  int64_t rl = rfirst;
-  double ya[4][4];
-  auto step = [&](const double (&db)[4][2]) {
+  double ring[4][4];
+  load(ring[0]);
+  load(ring[1]);
+  load(ring[2]);
+  const double *ucol = us + cl;
+  for (int64_t blk = 0; blk < nmine; ++blk) {
+    d4 acc[NX];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int k = 16 * ks + 4 * s + g;
-      const double2 y0 = *reinterpret_cast<const double2 *>(yl + k * w);
-      const double2 y1 = *reinterpret_cast<const double2 *>(yl + k * w + 2);
-      ya[s][0] = y0.x;
-      ya[s][1] = y0.y;
-      ya[s][2] = y1.x;
-      ya[s][3] = y1.y;
+    for (int x = 0; x < NX; ++x) acc[x] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < NK; ++ks) {
+      load(ring[(ks + 3) & 3]);
+      __builtin_amdgcn_sched_barrier(0);
+      const double (&db)[4] = ring[ks & 3];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double *urow = ucol + (16 * ks + 4 * s + g) * W;
+#pragma unroll
+        for (int x = ks; x < NX; ++x) acc[x] = mfma16x16x4(urow[16 * x], db[s], acc[x]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int x = 0; x < NX; ++x)
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x4(ya[s][x], db[s][y], acc[x][y]);
-    if (++ks == nk) {  // block done: every wave has read its X rows, then write
-      ks = 0;
-      __syncthreads();
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          const int col = c0 + 4 * g + 16 * e + x;
-          const double2 v = double2{acc[x][0][e], acc[x][1][e]};
-          *reinterpret_cast<double2 *>(X + (int64_t)col * ldx + rl) = v;
-          if (X2) *reinterpret_cast<double2 *>(X2 + (int64_t)col * ldx2 + rl) = v;
-        }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
-      rl += rstep;
-    }
-  };
-  double b0[4][2], b1[4][2], b2[4][2];
-  load(b0);
-  load(b1);
-  int64_t t = 0;
-  for (; t + 3 <= T; t += 3) {
-    load(b2);
-    __builtin_amdgcn_sched_barrier(0);
-    step(b0);
-    __builtin_amdgcn_sched_barrier(0);
-    load(b0);
-    __builtin_amdgcn_sched_barrier(0);
-    step(b1);
-    __builtin_amdgcn_sched_barrier(0);
-    load(b1);
-    __builtin_amdgcn_sched_barrier(0);
-    step(b2);
-    __builtin_amdgcn_sched_barrier(0);
+      for (int e = 0; e < 4; ++e) {
+        const int64_t off = (int64_t)(16 * x + g + 4 * e) * ldx + rl;
+        X[off] = acc[x][e];
+        if (X2) X2[(int64_t)(16 * x + g + 4 * e) * ldx2 + rl] = acc[x][e];
+      }
+    rl += rstep;
   }
-  if (t < T) step(b0);
-  if (t + 1 < T) step(b1);
 }
 
 // ----------------------------------------------------------------------------
@@ -1128,20 +1093,21 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
   }
   if (!subtract && ncg != 1) return hipErrorInvalidValue;  // in-place needs one column group
   if (!subtract && upper_y && batch == 1 && p == q && (q == 64 || q == 128) &&
-      m >= (q == 128 ? 128 : 256) && L == C &&
-      Cin == C && ldl == ldc && ldy == q && (ldc % 2 == 0) && ((uintptr_t)C % 16 == 0) &&
-      (!C2 || ((ldc2 % 2 == 0) && ((uintptr_t)C2 % 16 == 0)))) {
+      m >= kTrsmRows && L == C && Cin == C && ldl == ldc && ldy == q && (ldc % 2 == 0) &&
+      ((uintptr_t)C % 16 == 0) && (!C2 || ((ldc2 % 2 == 0) && ((uintptr_t)C2 % 16 == 0)))) {
     // in-place Q = X U^{-1}: persistent U^{-1}-in-LDS kernel over the full
     // row blocks, k_nn for the remaining rows
-    const int64_t brows = (q == 128) ? 128 : 256;
-    const int64_t mfull = m / brows * brows;  // > 0; the k_nn call below has m < brows
+    const int64_t mfull = m / kTrsmRows * kTrsmRows;  // > 0; the k_nn call below has m < 256
     {
       static bool attr = false;
       static int cus = 0;
       if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_trsm,
+        hipError_t e = hipFuncSetAttribute((const void *)k_trsm<128>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            kMaxPanel * kMaxPanel * (int)sizeof(double));
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute((const void *)k_trsm<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                64 * 64 * (int)sizeof(double));
         if (e != hipSuccess) return e;
         int dev = 0;
         e = hipGetDevice(&dev);
@@ -1150,11 +1116,14 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
         if (e != hipSuccess) return e;
         attr = true;
       }
-      const int64_t nblk = mfull / brows;
+      const int64_t nblk = mfull / kTrsmRows;
       const int64_t grid = std::min<int64_t>(nblk, std::max(cus, 1));
-      hipLaunchKernelGGL(k_trsm, dim3((unsigned)grid), dim3(512),
-                         (size_t)q * q * sizeof(double), s, mfull, q, C, ldc, Y, ldy, C2, ldc2,
-                         info);
+      if (q == 128)
+        hipLaunchKernelGGL(k_trsm<128>, dim3((unsigned)grid), dim3(512),
+                           (size_t)q * q * sizeof(double), s, mfull, C, ldc, Y, ldy, C2, ldc2, info);
+      else
+        hipLaunchKernelGGL(k_trsm<64>, dim3((unsigned)grid), dim3(512),
+                           (size_t)q * q * sizeof(double), s, mfull, C, ldc, Y, ldy, C2, ldc2, info);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess || mfull == m) return e;
     }

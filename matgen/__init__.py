@@ -66,25 +66,32 @@ def test_matrix(m: int, n: int, kappa: float, seed: int) -> np.ndarray:
     return np.asfortranarray(a)
 
 
-def gaussian_device(m: int, n: int, seed: int, device="cuda"):
+def gaussian_device(m: int, n: int, seed: int, device="cuda", ld: int | None = None):
     """Column-major m x n matrix of i.i.d. N(0,1) entries from torch's device
-    RNG (no factorisation involved); well conditioned for m >> n."""
+    RNG (no factorisation involved); well conditioned for m >> n. Stored
+    with leading dimension ld (default m)."""
     import torch
 
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed_sequence(seed, m, n, 7).generate_state(1, np.uint64)[0]) & ((1 << 63) - 1))
-    return torch.randn((n, m), dtype=torch.float64, device=device, generator=gen).t()
+    x = torch.randn((n, m), dtype=torch.float64, device=device, generator=gen).t()
+    if ld is None or ld == m:
+        return x
+    out = torch.empty((n, ld), dtype=torch.float64, device=device).t()[:m]
+    out.copy_(x)
+    return out
 
 
 def test_matrix_device(m: int, n: int, kappa: float, seed: int, device="cuda",
-                       chunk_rows: int = 1 << 16):
+                       chunk_rows: int = 1 << 16, ld: int | None = None):
     """Same recipe on a torch device; returns a column-major (m, n) view.
 
     U is built as the Q factor of an m x n Gaussian through a two-level
     Householder TSQR (chunks of ``chunk_rows`` rows, then the stacked R
     factors), which yields the same Q as one Householder QR of the whole
     Gaussian (the thin Q with positive-diagonal R is unique) while bounding
-    the QR workspace. The result is stored with stride (1, m).
+    the QR workspace. The result is stored with stride (1, ld), ld = m by
+    default.
     """
     import torch
 
@@ -98,7 +105,10 @@ def test_matrix_device(m: int, n: int, kappa: float, seed: int, device="cuda",
     v = torch.from_numpy(_haar_columns(rv, n, n)).to(device)
     sig = torch.from_numpy(log_spectrum(n, kappa)).to(device)
 
-    out = torch.empty((n, m), dtype=f64, device=device).t()  # column-major m x n
+    ld = m if ld is None else ld
+    if ld < m:
+        raise ValueError("need ld >= m")
+    out = torch.empty((n, ld), dtype=f64, device=device).t()[:m]  # column-major m x n
     nch = max(1, math.ceil(m / chunk_rows))
     if nch == 1 or m <= chunk_rows:
         g = torch.randn((m, n), dtype=f64, device=device, generator=gen)

@@ -273,6 +273,8 @@ def main():
                          "and launch shapes, no library QR in the profiled process)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="finish with one 1 GiB device copy (counter calibration)")
+    ap.add_argument("--no-staged", action="store_true",
+                    help="skip the extra timing of the same matrix with lda = m")
     ap.add_argument("--lda-pad", type=int, default=16,
                     help="store A and Q with leading dimension m + pad (0: lda = m, which "
                          "for m = 2^22 aliases cache sets and makes the library factor a "
@@ -377,7 +379,7 @@ def main():
         log(f"orthogonality {orth:.3e}  residual {res:.3e}  info {info}")
     value = householder_flops(m, n) / (ms * 1e-3) / 1e9
     staged = None
-    if args.lda_pad:
+    if args.lda_pad and not args.no_staged:
         # the same matrix stored with lda = m: the library factors a staging copy
         a2 = torch.empty((n, m), dtype=torch.float64, device=dev).t()
         a2.copy_(a)

@@ -19,6 +19,10 @@ Readings of the paper where it is silent:
 * The second CQRGS pass of CQR2GS uses the same panel width as the first.
 * mCQR2GS (Algorithm 9) leaves R implicit; R is assembled as derived in
   ``mcqr2gs``.
+* The run-time choice of CholeskyQR repetitions (section "Conclusion",
+  future work) is read as: leave a repetition out when its input's Gram
+  matrix is within a tolerance of I, and the re-orthogonalisation update
+  when its coefficients Z are below the tolerance (``mcqr2gs(adaptive=)``).
 * Shifted CholeskyQR (Algorithm 4): u is the unit roundoff of IEEE binary64,
   2^-53. ||A||_F^2 is the sum of the squared entries, per CHUNK-row block and
   then over blocks in the pairwise tree (the per-rank sums of section
@@ -182,7 +186,26 @@ def cqr2gs(a: np.ndarray, b: int):
     return q, r2 @ r1
 
 
-def mcqr2gs(a: np.ndarray, b: int):
+def _gram_distance(w: np.ndarray) -> float:
+    """||W - I||_F of a symmetric W, from its upper triangle."""
+    d = np.diag(w) - 1.0
+    up = np.triu(w, 1)
+    return float(np.sqrt(np.sum(d * d) + 2.0 * np.sum(up * up)))
+
+
+def _cqr_again(x: np.ndarray, col0: int, tol):
+    """The repeated CholeskyQR of a nearly orthonormal X. With tol set it is
+    left out (Q = X, U = I) when the Gram matrix of X is within tol of I in
+    the Frobenius norm: the repetition could only move the orthogonality
+    from ||X^T X - I||_F to O(u)."""
+    if tol is not None:
+        w = gram(x)
+        if _gram_distance(w) <= tol:
+            return x.copy(), np.eye(x.shape[1])
+    return cqr(x, col0)
+
+
+def mcqr2gs(a: np.ndarray, b: int, adaptive=None):
     """Modified CholeskyQR2 with Gram-Schmidt (mCQR2GS), Algorithm 9.
 
     Steps per panel j >= 2 (1-based as in the paper):
@@ -194,13 +217,24 @@ def mcqr2gs(a: np.ndarray, b: int):
     gives R_{1:j-1,j} += Z Ua and R_jj = Ub Ua. The first panel is CQR2
     (Algorithm 9, first line). The paper does not write R for this algorithm;
     this is the bookkeeping that makes A = Q R hold.
+
+    adaptive = tol (the run-time choice of repetitions the paper proposes in
+    its conclusion): a repeated CholeskyQR is left out when the Gram matrix
+    of its input is within tol of I (``_cqr_again``), and the
+    re-orthogonalisation update when ||Z||_F <= tol (Z := 0), which changes
+    Q_j's orthogonality to the earlier panels by at most ||Z||_F.
     """
     m, n = a.shape
     x = np.array(a, dtype=np.float64, order="F", copy=True)
     r = np.zeros((n, n))
     pan = _panels(n, b)
     s0, e0 = pan[0]
-    x[:, s0:e0], r[s0:e0, s0:e0] = cqr2(x[:, s0:e0], s0)
+    if adaptive is None:
+        x[:, s0:e0], r[s0:e0, s0:e0] = cqr2(x[:, s0:e0], s0)
+    else:
+        q1, r1 = cqr(x[:, s0:e0], s0)
+        q2, r2 = _cqr_again(q1, s0, adaptive)
+        x[:, s0:e0], r[s0:e0, s0:e0] = q2, r2 @ r1
     for jj in range(1, len(pan)):
         ps, pe = pan[jj - 1]
         s, e = pan[jj]
@@ -209,8 +243,10 @@ def mcqr2gs(a: np.ndarray, b: int):
         r[ps:pe, s:] = y                          # R_{j-1,j:k} := Y
         qt, ua = cqr(x[:, s:e], s)                # CQR(A_j)
         z = xprod(x[:, :s], qt)                   # Q_{1:j-1}^T A_j
+        if adaptive is not None and np.linalg.norm(z) <= adaptive:
+            z = np.zeros_like(z)                  # orthogonal enough: no update
         qt = qt - x[:, :s] @ z                    # A_j -= Q_{1:j-1} Q_{1:j-1}^T A_j
-        qj, ub = cqr(qt, s)                       # Q_j = CQR(A_j)
+        qj, ub = _cqr_again(qt, s, adaptive)      # Q_j = CQR(A_j)
         x[:, s:e] = qj
         r[:s, s:e] += z @ ua
         r[s:e, s:e] = ub @ ua

@@ -228,6 +228,48 @@ def bench_scqr3(steps: int, warmup: int):
     return out
 
 
+def bench_adaptive(steps: int, warmup: int):
+    """The run-time choice of CholeskyQR repetitions (adaptive) against the
+    plain mCQR2GS at 2^20 x 256, b = 64, lda = m + 16: at kappa = 1 every
+    repetition is left out, at kappa = 1e5 none is."""
+    import torch
+    import matgen
+    import paper_2405_04237_amd as cqr
+    from paper_2405_04237_amd import measure
+
+    m, n, b = 1 << 20, 256, 64
+    dev = torch.device("cuda:0")
+    out = {"workload": f"{m} x {n}, b = {b}, lda {m + 16}"}
+    for kappa in (1.0, 1e5):
+        a = matgen.test_matrix_device(m, n, kappa, seed=61, device=dev, ld=m + 16)
+        q = cqr.empty_colmajor(m, n, dev, ld=a.stride(1))
+        r = cqr.empty_colmajor(n, n, dev)
+        ws = cqr.Workspace(m, n, b, "mod", dev)
+        res = {}
+        for mode in (False, True):
+            def step():
+                cqr.qr(a, b=b, schedule="mod", out=(q, r), workspace=ws, check=False, adaptive=mode)
+
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            res["adaptive" if mode else "plain"] = {
+                "ms": round(e0.elapsed_time(e1) / steps, 3),
+                "orthogonality": measure.orthogonality(q), "residual": measure.residual(a, q, r),
+                "info": int(ws.info.item())}
+        out[f"kappa={kappa:.0e}"] = res
+        log(f"adaptive leg, kappa {kappa:.0e}: " + json.dumps({k: v["ms"] for k, v in res.items()}))
+        del a, q, r, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w: dict, b: int, schedule: str, rows: int):
     """The oracle, untuned, on a row sample of the workload (host cores)."""
     import numpy as np
@@ -422,6 +464,7 @@ def main():
         out["backward"] = bench_backward(max(args.steps, 5), 2)
         log("backward: " + json.dumps(out["backward"]))
         out["scqr3"] = bench_scqr3(max(args.steps, 5), 2)
+        out["adaptive"] = bench_adaptive(max(args.steps, 5), 2)
     if args.calibration_copy:
         x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         y = torch.ones(1 << 27, dtype=torch.float64, device=dev)

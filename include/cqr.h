@@ -103,7 +103,21 @@ typedef struct cqr_options {
                               lookahead = 0. 0: everything on `stream`. Zero-
                               initialise the struct; other schedules ignore
                               it. */
+  int adaptive;            /* CQR_SCHED_MOD only. 1: the run-time choice of
+                              CholeskyQR repetitions the paper proposes as
+                              future work (section "Conclusion"): a repeated
+                              CholeskyQR of a panel is left out (U = I) when
+                              its input's Gram matrix W has ||W - I||_F <=
+                              CQR_ADAPTIVE_TOL, and the re-orthogonalisation
+                              update when its coefficients have ||Z||_F <=
+                              CQR_ADAPTIVE_TOL (Z := 0). Decided on the device
+                              (no synchronisation); the accuracy bounds are
+                              kept, and well-conditioned panels cost fewer
+                              passes. 0: every repetition runs. */
 } cqr_options;
+
+/* Tolerance of cqr_options.adaptive (a Frobenius norm). */
+#define CQR_ADAPTIVE_TOL 1e-14
 
 /* Factor A = Q R with the default schedule (mCQR2GS). Q has leading
  * dimension lda, R leading dimension n. Uses the library's internal

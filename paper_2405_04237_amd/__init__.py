@@ -71,14 +71,16 @@ class Workspace:
 
 
 def qr(a, b: int = 0, schedule: str = "mod", check: bool = True, out=None,
-       workspace: Workspace | None = None, lookahead: bool = False):
+       workspace: Workspace | None = None, lookahead: bool = False, adaptive: bool = False):
     """Thin QR of a tall-and-skinny FP64 matrix: returns (Q, R).
 
     schedule "mod" = mCQR2GS (Algorithm 9), "orig" = CQR2GS (Algorithm 7),
     "scqr3" = shifted CholeskyQR3 (Algorithm 5; whole matrix, n <= 128, b
     ignored). b = 0 picks libcqr's default panel width. lookahead=True runs
     each mCQR2GS panel's chain on a side stream, overlapped with the trailing
-    update (bitwise the same result). With check=True the call waits
+    update (bitwise the same result). adaptive=True leaves out a panel's
+    repeated CholeskyQR or re-orthogonalisation update when it is within
+    libcqr's tolerance of doing nothing (mCQR2GS only). With check=True the call waits
     for the device and raises Breakdown if a Cholesky pivot failed;
     otherwise the caller reads ``workspace.info``.
     """
@@ -101,7 +103,7 @@ def qr(a, b: int = 0, schedule: str = "mod", check: bool = True, out=None,
     stream = torch.cuda.current_stream(a.device).cuda_stream
     st = _lib.factor_ex(m, n, b, a.data_ptr(), lda, q.data_ptr(), r.data_ptr(), stream,
                         SCHEDULES[schedule], workspace.info.data_ptr(),
-                        workspace.buf.data_ptr(), workspace.bytes, lookahead)
+                        workspace.buf.data_ptr(), workspace.bytes, lookahead, adaptive)
     _lib.check(st, "cqr_factor_ex")
     if check:
         col = int(workspace.info.item())

@@ -33,7 +33,7 @@ _I64, _VP, _DP = C.c_int64, C.c_void_p, C.c_void_p
 
 class CqrOptions(C.Structure):
     _fields_ = [("schedule", C.c_int), ("d_info", C.c_void_p), ("workspace", C.c_void_p),
-                ("workspace_bytes", C.c_size_t), ("lookahead", C.c_int)]
+                ("workspace_bytes", C.c_size_t), ("lookahead", C.c_int), ("adaptive", C.c_int)]
 
 
 SIGNATURES = {
@@ -97,8 +97,9 @@ def default_panel(m: int, n: int, schedule: int) -> int:
 
 
 def factor_ex(m, n, b, a_ptr, lda, q_ptr, r_ptr, stream, schedule, info_ptr, ws_ptr, ws_bytes,
-              lookahead=False):
-    opt = CqrOptions(schedule, info_ptr, ws_ptr, ws_bytes, 1 if lookahead else 0)
+              lookahead=False, adaptive=False):
+    opt = CqrOptions(schedule, info_ptr, ws_ptr, ws_bytes, 1 if lookahead else 0,
+                     1 if adaptive else 0)
     return int(lib().cqr_factor_ex(m, n, b, a_ptr, lda, q_ptr, r_ptr, stream, C.byref(opt)))
 
 

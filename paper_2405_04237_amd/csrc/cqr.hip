@@ -63,7 +63,7 @@ int64_t staging_ld(int64_t m) {
 
 // ---------------------------------------------------------------- workspace
 struct Layout {
-  int64_t w, uinv, ua, ub, y, yz, part, r1, r2, stage, total;  // byte offsets / size
+  int64_t w, uinv, ua, ub, y, yz, part, r1, r2, stage, flags, total;  // byte offsets / size
   int64_t part_elems, ldw;                                 // ldw: staging leading dim
 };
 
@@ -75,6 +75,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t b, int schedule, bool stage) {
     off = round_up(off + elems * 8, kAlign);
     return o;
   };
+  L.flags = take(32);  // adaptive repetition decisions (ints)
   L.w = take(b * b);
   L.uinv = take(b * cqr::padded_ld(b));
   L.ua = take(b * b);
@@ -204,6 +205,8 @@ struct Run {
   hipStream_t aux;               // look-ahead side stream (null: none)
   hipEvent_t fork, join;         // main -> aux and aux -> main
   double *Yz;                    // Z buffer of the look-ahead chain
+  double adaptive;               // > 0: tolerance of the run-time repetition choice
+  int *zskip, *cskip;            // its decisions (device words)
   int *info;
   int64_t m, n;
   double *W, *Uinv, *Ua, *Ub, *Y, *part, *R1, *R2;
@@ -241,22 +244,30 @@ hipError_t step_gram(Run &r, const double *X, int64_t ldx, int w) {
   });
 }
 
-// U = chol(W), Uinv = U^{-1}; U optionally to uout (row-major) and/or the R block
-hipError_t step_chol(Run &r, int w, double *uout, double *rblk, int64_t ldr, int col0) {
+// U = chol(W), Uinv = U^{-1}; U optionally to uout (row-major) and/or the R block.
+// skip: a repeated CholeskyQR under the run-time choice (U = I when W is
+// within r.adaptive of I; the decision goes to *skip).
+hipError_t step_chol(Run &r, int w, double *uout, double *rblk, int64_t ldr, int col0,
+                     int *skip = nullptr) {
   const double wf = w;
   return timed(r.s, CQR_K_CHOL, 2.0 * wf * wf * wf / 3.0, 8.0 * 4 * wf * wf, [&] {
-    return cqr::launch_chol_inv(r.W, w, uout, rblk, ldr, r.Uinv, r.info, col0, r.s);
+    return cqr::launch_chol_inv(r.W, w, uout, rblk, ldr, r.Uinv, r.info, col0, r.s, r.adaptive,
+                                skip);
   });
 }
 
 // Q = X U^{-1} (the Q_j := A_j U^{-1} step); Q may be X (in place). col >= 0
 // marks the panel's final Q, which a staged run also writes to the caller's
 // Q at that column.
-hipError_t step_trsm(Run &r, const double *X, double *Qo, int64_t ld, int w, int64_t col = -1) {
+// skip: U^{-1} may be I by the run-time choice; an in-place product without a
+// second destination is then left out.
+hipError_t step_trsm(Run &r, const double *X, double *Qo, int64_t ld, int w, int64_t col = -1,
+                     const int *skip = nullptr) {
   double *q2 = (col >= 0 && r.Qout) ? r.Qout + col * r.ldq : nullptr;
+  const int *sk = (X == Qo && !q2) ? skip : nullptr;
   return timed(r.s, CQR_K_TRSM, double(r.m) * w * w, (q2 ? 24.0 : 16.0) * r.m * w, [&] {
     return cqr::launch_nn(false, true, r.m, w, w, X, ld, r.Uinv, cqr::padded_ld(w), nullptr, ld, Qo,
-                          ld, r.info, r.s, nullptr, 0, 0, 1, 0, 0, 0, 0, 0, q2, r.ldq);
+                          ld, r.info, r.s, nullptr, 0, 0, 1, 0, 0, 0, 0, 0, q2, r.ldq, sk);
   });
 }
 
@@ -276,18 +287,22 @@ hipError_t step_proj(Run &r, const double *Qp, int64_t ld, int p, const double *
 }
 
 // Zo = Zi - Qp Y with Ym = -Y (row-major, leading dim ldy); Zo may be Zi
+// skip (in place only): Y may have been set to 0 by the run-time choice,
+// and the update is then left out.
 hipError_t step_update_y(Run &r, const double *Qp, int64_t ld, int p, const double *Zi, double *Zo,
-                         int q, const double *Ym, int64_t ldy) {
+                         int q, const double *Ym, int64_t ldy, const int *skip = nullptr) {
   const int kind = cqr::nn_short_k(p, Qp, ld, Zi, ld, Zo, ld) ? CQR_K_UPDATE : CQR_K_UPDATE_LONG;
+  const int *sk = (Zi == Zo) ? skip : nullptr;
   return timed(r.s, kind, 2.0 * r.m * p * q, 8.0 * r.m * (p + 2.0 * q), [&] {
-    return cqr::launch_nn(true, false, r.m, p, q, Qp, ld, Ym, ldy, Zi, ld, Zo, ld, r.info, r.s);
+    return cqr::launch_nn(true, false, r.m, p, q, Qp, ld, Ym, ldy, Zi, ld, Zo, ld, r.info, r.s,
+                          nullptr, 0, 0, 1, 0, 0, 0, 0, 0, nullptr, 0, sk);
   });
 }
 
 // Zo = Zi - Qp Y  (r.Y holds -Y for these q columns); Zo may be Zi (in place)
 hipError_t step_update(Run &r, const double *Qp, int64_t ld, int p, const double *Zi, double *Zo,
-                       int q) {
-  return step_update_y(r, Qp, ld, p, Zi, Zo, q, r.Y, cqr::padded_ld(q));
+                       int q, const int *skip = nullptr) {
+  return step_update_y(r, Qp, ld, p, Zi, Zo, q, r.Y, cqr::padded_ld(q), skip);
 }
 
 // One CQRGS pass (Algorithm 6; Algorithm 8 with the Allreduces replaced by
@@ -372,9 +387,10 @@ hipError_t run_mod(Run &r, const double *A, double *Q, int64_t ld, int64_t b, do
     CQR_TRY(step_gram(r, A, ld, w));
     CQR_TRY(step_chol(r, w, r.Ua, nullptr, 0, 0));
     CQR_TRY(step_trsm(r, A, Q, ld, w));
+    int *cs = r.adaptive > 0 ? r.cskip : nullptr;
     CQR_TRY(step_gram(r, Q, ld, w));
-    CQR_TRY(step_chol(r, w, r.Ub, nullptr, 0, 0));
-    CQR_TRY(step_trsm(r, Q, Q, ld, w, 0));
+    CQR_TRY(step_chol(r, w, r.Ub, nullptr, 0, 0, cs));
+    CQR_TRY(step_trsm(r, Q, Q, ld, w, 0, cs));
     CQR_TRY(timed(r.s, CQR_K_SMALL, 0, 0, [&] {
       return cqr::launch_r_upper_product(w, r.Ub, r.Ua, R, n, r.info, r.s);  // R_11 = R2 R1
     }));
@@ -410,14 +426,22 @@ hipError_t run_mod(Run &r, const double *A, double *Q, int64_t ld, int64_t b, do
     // re-orthogonalise: Z := Q_{1:j-1}^T Qt; Qt -= Q_{1:j-1} Z; R_{1:j-1,j} += Z Ua
     // (c.Y holds -Z, so the R update subtracts (-Z) Ua)
     CQR_TRY(step_proj(c, Q, ld, (int)s, Xj, w, nullptr, 0));
-    CQR_TRY(step_update(c, Q, ld, (int)s, Xj, Xj, w));
+    int *zs = nullptr, *cs = nullptr;
+    if (c.adaptive > 0) {  // run-time choice: Z := 0 when ||Z||_F is within the tolerance
+      zs = c.zskip;
+      cs = c.cskip;
+      CQR_TRY(timed(c.s, CQR_K_SMALL, 2.0 * s * w, 8.0 * s * w, [&] {
+        return cqr::launch_zskip(c.Y, (int)s, w, cqr::padded_ld(w), c.adaptive, zs, c.info, c.s);
+      }));
+    }
+    CQR_TRY(step_update(c, Q, ld, (int)s, Xj, Xj, w, zs));
     CQR_TRY(timed(c.s, CQR_K_SMALL, 2.0 * s * w * w / 2, 0, [&] {
       return cqr::launch_r_add_zu((int)s, w, c.Y, cqr::padded_ld(w), c.Ua, R + s * n, n, c.info, c.s);
     }));
     // CQR again: Qt = Q_j Ub; R_jj = Ub Ua
     CQR_TRY(step_gram(c, Xj, ld, w));
-    CQR_TRY(step_chol(c, w, c.Ub, nullptr, 0, (int)s));
-    CQR_TRY(step_trsm(c, Xj, Xj, ld, w, s));
+    CQR_TRY(step_chol(c, w, c.Ub, nullptr, 0, (int)s, cs));
+    CQR_TRY(step_trsm(c, Xj, Xj, ld, w, s, cs));
     CQR_TRY(timed(c.s, CQR_K_SMALL, 0, 0, [&] {
       return cqr::launch_r_upper_product(w, c.Ub, c.Ua, R + s + s * n, n, c.info, c.s);
     }));
@@ -578,6 +602,9 @@ int cqr_factor_ex(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
   r.R1 = lay.r1 >= 0 ? (double *)(ws + lay.r1) : nullptr;
   r.R2 = lay.r2 >= 0 ? (double *)(ws + lay.r2) : nullptr;
   r.Yz = lay.yz >= 0 ? (double *)(ws + lay.yz) : nullptr;
+  r.zskip = (int *)(ws + lay.flags);
+  r.cskip = r.zskip + 1;
+  r.adaptive = (opt && opt->adaptive && schedule == CQR_SCHED_MOD) ? CQR_ADAPTIVE_TOL : 0.0;
   std::unique_lock<std::mutex> side_lock;
   if (opt && opt->lookahead && schedule == CQR_SCHED_MOD && r.Yz && be < n) {
     DevState *ds = nullptr;

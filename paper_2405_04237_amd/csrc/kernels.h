@@ -42,12 +42,16 @@ int64_t tn_tiles(bool gram, int p, int q, bool same = false);
 // [L(:, 0:psplit) | L2]. L2 = nullptr means L alone.
 // C2/ldc2 (subtract = false, batch = 1 only): a second destination that
 // receives the same values as C.
+// skip (optional): the kernels do nothing when *skip != 0 at run time (the
+// caller has made the product an identity: Y = 0 for an update, Y = I for
+// an in-place product).
 hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const double *L,
                      int64_t ldl, const double *Y, int64_t ldy, const double *Cin, int64_t ldci,
                      double *C, int64_t ldc, const int *info, hipStream_t s,
                      const double *L2 = nullptr, int64_t ldl2 = 0, int psplit = 0, int batch = 1,
                      int64_t sL = 0, int64_t sL2 = 0, int64_t sY = 0, int64_t sCin = 0,
-                     int64_t sC = 0, double *C2 = nullptr, int64_t ldc2 = 0);
+                     int64_t sC = 0, double *C2 = nullptr, int64_t ldc2 = 0,
+                     const int *skip = nullptr);
 
 // True when launch_nn runs a single-matrix subtract = true product through
 // the short-inner-dimension kernel (Y staged in LDS); false: the general one.
@@ -73,8 +77,17 @@ hipError_t launch_reduce(bool gram, double *part, int64_t nch, int p, int q, dou
 // the R block rblk (if non-null, strict lower part set to 0), U^{-1}
 // row-major with leading dimension padded_ld(w) to uinv (strict lower part 0). A pivot that is not > 0 sets *info = col0 + i
 // + 1 (first failure wins) and leaves the outputs undefined.
+// skip (optional): first ||W - I||_F is summed in a fixed order; if it is
+// <= skip_tol the outputs are U = U^{-1} = I and *skip = 1 (no Cholesky),
+// else *skip = 0.
 hipError_t launch_chol_inv(const double *W, int w, double *uout, double *rblk, int64_t ldr,
-                           double *uinv, int *info, int col0, hipStream_t s);
+                           double *uinv, int *info, int col0, hipStream_t s,
+                           double skip_tol = 0.0, int *skip = nullptr);
+
+// ||Z||_F of the rows x cols row-major Z (leading dim ldz), fixed order; if
+// <= tol, Z := 0 and *skip = 1, else *skip = 0. One workgroup.
+hipError_t launch_zskip(double *Z, int rows, int cols, int64_t ldz, double tol, int *skip,
+                        const int *info, hipStream_t s);
 
 // Rinv = R^{-1} for `batch` upper triangular n x n matrices (R column-major
 // ld n at R + i*sR; Rinv row-major ld n at Rinv + i*sRi); n <= kMaxPanel.

@@ -502,9 +502,10 @@ __global__ __launch_bounds__(256, (RB == 2) ? 2 : 1) void k_nn(
     int64_t m, int p, int q, const double *L, int64_t ldl, const double *L2, int64_t ldl2,
     int psplit, const double *__restrict__ Y, int64_t ldy, const double *Cin, int64_t ldci,
     double *C, int64_t ldc, int wr, int ncg, int64_t sL, int64_t sL2, int64_t sY, int64_t sCin,
-    int64_t sC, double *C2, int64_t ldc2, const int *__restrict__ info) {
+    int64_t sC, double *C2, int64_t ldc2, const int *__restrict__ info,
+    const int *__restrict__ skip) {
   constexpr int kRows = 16 * RB;  // rows of a wave's tile
-  if (*info) return;
+  if (*info || (skip && *skip)) return;
   {  // batch: one matrix per grid row
     const int64_t bi = blockIdx.y;
     L += bi * sL;
@@ -695,9 +696,10 @@ __global__ __launch_bounds__(256, 2) void k_upd(int64_t m, int p, int q, const d
                                                 int64_t ldl, const double *__restrict__ Y,
                                                 int64_t ldy, const double *Cin, int64_t ldci,
                                                 double *C, int64_t ldc, int nslab,
-                                                int64_t rows_per_wg, const int *__restrict__ info) {
+                                                int64_t rows_per_wg, const int *__restrict__ info,
+                                                const int *__restrict__ skip) {
   extern __shared__ double ys[];  // [pp][64], row-major
-  if (*info) return;
+  if (*info || (skip && *skip)) return;
   const int64_t lid = xcd_logical(blockIdx.x, gridDim.x);
   const int c0 = (int)(lid % nslab) * kTile;
   const int64_t rb = (lid / nslab) * rows_per_wg;
@@ -851,9 +853,10 @@ template <int W>
 __global__ __launch_bounds__(512, 1) void k_trsm(int64_t mfull, double *X, int64_t ldx,
                                                  const double *__restrict__ Uinv, int64_t ldu,
                                                  double *X2, int64_t ldx2,
-                                                 const int *__restrict__ info) {
+                                                 const int *__restrict__ info,
+                                                 const int *__restrict__ skip) {
   extern __shared__ double us[];  // [W][W] row-major
-  if (*info) return;
+  if (*info || (skip && *skip)) return;
   for (int e = threadIdx.x; e < W * W; e += 512) {
     const int k = e / W, c = e % W;
     us[e] = (c >= k) ? Uinv[(int64_t)k * ldu + c] : 0.0;
@@ -1045,7 +1048,7 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
                      int64_t ldl, const double *Y, int64_t ldy, const double *Cin, int64_t ldci,
                      double *C, int64_t ldc, const int *info, hipStream_t s, const double *L2,
                      int64_t ldl2, int psplit, int batch, int64_t sL, int64_t sL2, int64_t sY,
-                     int64_t sCin, int64_t sC, double *C2, int64_t ldc2) {
+                     int64_t sCin, int64_t sC, double *C2, int64_t ldc2, const int *skip) {
   if (C2 && (subtract || batch != 1)) return hipErrorInvalidValue;
   if (!L2) {
     L2 = L;
@@ -1120,15 +1123,18 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
       const int64_t grid = std::min<int64_t>(nblk, std::max(cus, 1));
       if (q == 128)
         hipLaunchKernelGGL(k_trsm<128>, dim3((unsigned)grid), dim3(512),
-                           (size_t)q * q * sizeof(double), s, mfull, C, ldc, Y, ldy, C2, ldc2, info);
+                           (size_t)q * q * sizeof(double), s, mfull, C, ldc, Y, ldy, C2, ldc2, info,
+                           skip);
       else
         hipLaunchKernelGGL(k_trsm<64>, dim3((unsigned)grid), dim3(512),
-                           (size_t)q * q * sizeof(double), s, mfull, C, ldc, Y, ldy, C2, ldc2, info);
+                           (size_t)q * q * sizeof(double), s, mfull, C, ldc, Y, ldy, C2, ldc2, info,
+                           skip);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess || mfull == m) return e;
     }
     return launch_nn(false, true, m - mfull, p, q, L + mfull, ldl, Y, ldy, nullptr, 0, C + mfull,
-                     ldc, info, s, nullptr, 0, 0, 1, 0, 0, 0, 0, 0, C2 ? C2 + mfull : nullptr, ldc2);
+                     ldc, info, s, nullptr, 0, 0, 1, 0, 0, 0, 0, 0, C2 ? C2 + mfull : nullptr, ldc2,
+                     skip);
   }
   if (subtract && batch == 1 && psplit == p && nn_short_k(p, L, ldl, Cin, ldci, C, ldc)) {
     // one round of resident workgroups (two per CU): each slab gets an equal
@@ -1153,7 +1159,7 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
     const int64_t chunks = (m + rpw - 1) / rpw;
     const size_t lds = (size_t)((p + 15) / 16 * 16) * kTile * sizeof(double);
     hipLaunchKernelGGL(k_upd, dim3((unsigned)(chunks * slabs)), dim3(256), lds, s, m, p, q, L, ldl,
-                       Y, ldy, Cin, ldci, C, ldc, slabs, rpw, info);
+                       Y, ldy, Cin, ldci, C, ldc, slabs, rpw, info, skip);
     return hipGetLastError();
   }
   const int64_t rows = 16 * kNnRB * (int64_t)wr;
@@ -1166,7 +1172,8 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
   dim3 grid((unsigned)(rts * ncg), (unsigned)batch), block(256);
 #define CQR_NN(S, T, V)                                                                             \
   hipLaunchKernelGGL((k_nn<S, T, V, kNnRB>), grid, block, 0, s, m, p, q, L, ldl, L2, ldl2, psplit, \
-                     Y, ldy, Cin, ldci, C, ldc, wr, ncg, sL, sL2, sY, sCin, sC, C2, ldc2, info)
+                     Y, ldy, Cin, ldci, C, ldc, wr, ncg, sL, sL2, sY, sCin, sC, C2, ldc2, info, \
+                     skip)
   if (subtract) {
     if (vec) CQR_NN(true, false, true); else CQR_NN(true, false, false);
   } else if (upper_y) {
@@ -1311,9 +1318,10 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double *__restr
                                                            double *__restrict__ uout,
                                                            double *__restrict__ rblk, int64_t ldr,
                                                            double *__restrict__ uinv, int *info,
-                                                           int col0) {
+                                                           int col0, double skip_tol, int *skip) {
   extern __shared__ double S[];  // wp x wp, then the inverse's scratch
   __shared__ int flag;
+  __shared__ double red[kCholThreads];
   if (*info) return;
   const int tid = threadIdx.x, nt = blockDim.x, wp = blocked_order(w);
   for (int e = tid; e < wp * wp; e += nt) {
@@ -1321,6 +1329,38 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double *__restr
     S[e] = (i < w && j < w) ? ((i <= j) ? W[i * w + j] : 0.0) : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
+  if (skip) {
+    // ||W - I||_F from the upper triangle, summed in a fixed order (each
+    // thread its strided elements in turn, then a fixed tree); within the
+    // tolerance the factor is U = I and the step it feeds is left out
+    double acc = 0.0;
+    for (int e = tid; e < w * w; e += nt) {
+      const int i = e / w, j = e % w;
+      if (i <= j) {
+        const double v = S[i * wp + j] - (i == j ? 1.0 : 0.0);
+        acc += (i == j ? 1.0 : 2.0) * v * v;
+      }
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (int h = kCholThreads / 2; h > 0; h >>= 1) {
+      if (tid < h) red[tid] += red[tid + h];
+      __syncthreads();
+    }
+    const bool near = sqrt(red[0]) <= skip_tol;
+    if (tid == 0) *skip = near ? 1 : 0;
+    if (near) {
+      for (int e = tid; e < w * w; e += nt) {
+        const int i = e / w, j = e % w;
+        const double u = (i == j) ? 1.0 : 0.0;
+        if (uout) uout[e] = u;
+        if (rblk) rblk[i + (int64_t)j * ldr] = u;
+      }
+      const int ldu = (int)padded_ld(w);
+      for (int e = tid; e < w * ldu; e += nt) uinv[e] = (e / ldu == e % ldu) ? 1.0 : 0.0;
+      return;
+    }
+  }
   const int fail = lds_cholesky_blocked(S, wp, &flag);
   if (fail) {
     if (tid == 0) atomicCAS(info, 0, col0 + fail);
@@ -1342,7 +1382,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double *__restr
 }
 
 hipError_t launch_chol_inv(const double *W, int w, double *uout, double *rblk, int64_t ldr,
-                           double *uinv, int *info, int col0, hipStream_t s) {
+                           double *uinv, int *info, int col0, hipStream_t s, double skip_tol,
+                           int *skip) {
   if (w < 1 || w > kMaxPanel) return hipErrorInvalidValue;
   const int wp = blocked_order(w);
   const size_t lds = (size_t)blocked_lds_doubles(wp) * sizeof(double);
@@ -1355,7 +1396,7 @@ hipError_t launch_chol_inv(const double *W, int w, double *uout, double *rblk, i
     attr_set = true;
   }
   hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kCholThreads), lds, s, W, w, uout, rblk, ldr, uinv,
-                     info, col0);
+                     info, col0, skip_tol, skip);
   return hipGetLastError();
 }
 
@@ -1554,6 +1595,43 @@ __global__ __launch_bounds__(256) void k_shift_diag(double *W, int w, double sqr
 hipError_t launch_shift_diag(double *W, int w, double sqrt_m_u, const int *info, hipStream_t s) {
   if (w < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_shift_diag, dim3(1), dim3(256), 0, s, W, w, sqrt_m_u, info);
+  return hipGetLastError();
+}
+
+// Adaptive re-orthogonalisation: ||Z||_F of the rows x cols row-major Z
+// (leading dim ldz) in a fixed order; within tol, Z := 0 and *skip = 1 (the
+// update that would apply Z is then left out), else *skip = 0.
+__global__ __launch_bounds__(512) void k_zskip(double *Z, int rows, int cols, int64_t ldz,
+                                               double tol, int *skip, const int *__restrict__ info) {
+  __shared__ double red[512];
+  __shared__ int near;
+  if (*info) return;
+  const int tid = threadIdx.x;
+  const int64_t count = (int64_t)rows * cols;
+  double acc = 0.0;
+  for (int64_t e = tid; e < count; e += 512) {
+    const double v = Z[(e / cols) * ldz + e % cols];
+    acc += v * v;
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int h = 256; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    near = sqrt(red[0]) <= tol ? 1 : 0;
+    *skip = near;
+  }
+  __syncthreads();
+  if (near)
+    for (int64_t e = tid; e < count; e += 512) Z[(e / cols) * ldz + e % cols] = 0.0;
+}
+
+hipError_t launch_zskip(double *Z, int rows, int cols, int64_t ldz, double tol, int *skip,
+                        const int *info, hipStream_t s) {
+  if (rows < 1 || cols < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_zskip, dim3(1), dim3(512), 0, s, Z, rows, cols, ldz, tol, skip, info);
   return hipGetLastError();
 }
 

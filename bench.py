@@ -270,6 +270,60 @@ def bench_adaptive(steps: int, warmup: int):
     return out
 
 
+def bench_small_graph(steps: int):
+    """The small single-matrix workload (4096 x 64, b = 16, kappa = 1e12):
+    eager calls against replays of one HIP graph holding the whole
+    factorisation (the launch-bound case)."""
+    import torch
+    import matgen
+    import paper_2405_04237_amd as cqr
+    from paper_2405_04237_amd.costs import householder_flops
+
+    m, n, b = 4096, 64, 16
+    dev = torch.device("cuda:0")
+    a = matgen.test_matrix_device(m, n, 1e12, seed=1, device=dev)
+    ws = cqr.Workspace(m, n, b, "mod", dev)
+    q = cqr.empty_colmajor(m, n, dev, ld=a.stride(1))
+    r = cqr.empty_colmajor(n, n, dev)
+
+    def step():
+        cqr.qr(a, b=b, schedule="mod", out=(q, r), workspace=ws, check=False)
+
+    reps = max(steps, 50)
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    eager = e0.elapsed_time(e1) / reps
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            step()
+    torch.cuda.current_stream().wait_stream(s)
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    graph = e0.elapsed_time(e1) / reps
+    hf = householder_flops(m, n)
+    log(f"small single matrix: eager {eager:.3f} ms, graph {graph:.3f} ms")
+    return {"workload": f"{m} x {n}, b = {b}, kappa=1e12", "reps": reps,
+            "eager_ms": round(eager, 4), "graph_ms": round(graph, 4),
+            "eager_gflops_hh": round(hf / (eager * 1e-3) / 1e9, 1),
+            "graph_gflops_hh": round(hf / (graph * 1e-3) / 1e9, 1), "info": int(ws.info.item())}
+
+
 def cpu_baseline(w: dict, b: int, schedule: str, rows: int):
     """The oracle, untuned, on a row sample of the workload (host cores)."""
     import numpy as np
@@ -465,6 +519,7 @@ def main():
         log("backward: " + json.dumps(out["backward"]))
         out["scqr3"] = bench_scqr3(max(args.steps, 5), 2)
         out["adaptive"] = bench_adaptive(max(args.steps, 5), 2)
+        out["small_graph"] = bench_small_graph(args.steps)
     if args.calibration_copy:
         x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         y = torch.ones(1 << 27, dtype=torch.float64, device=dev)

@@ -844,13 +844,15 @@ __global__ __launch_bounds__(256, 2) void k_upd(int64_t m, int p, int q, const d
 //   B operand (X): lane holds X[r + cl][k]
 //   D element e of block x: Q[r + cl][16x + g + 4e]
 // The k steps of consecutive blocks form one stream through a four-deep
-// register ring (prefetch three steps ahead). X2 (optional) receives the
-// same values as X.
+// register ring (prefetch three steps ahead). The product reads Xs (ld
+// ldxs) and writes X: Xs = X is the in-place form, any other Xs must not
+// overlap X. X2 (optional) receives the same values as X.
 // ----------------------------------------------------------------------------
 constexpr int kTrsmRows = 128;
 
 template <int W>
-__global__ __launch_bounds__(512, 1) void k_trsm(int64_t mfull, double *X, int64_t ldx,
+__global__ __launch_bounds__(512, 1) void k_trsm(int64_t mfull, const double *Xs, int64_t ldxs,
+                                                 double *X, int64_t ldx,
                                                  const double *__restrict__ Uinv, int64_t ldu,
                                                  double *X2, int64_t ldx2,
                                                  const int *__restrict__ info,
@@ -872,15 +874,15 @@ __global__ __launch_bounds__(512, 1) void k_trsm(int64_t mfull, double *X, int64
   const int64_t rstep = (int64_t)gridDim.x * kTrsmRows;  // rows between this workgroup's blocks
   int64_t rl = (int64_t)blockIdx.x * kTrsmRows + 16 * wave + cl;
 
-  // load cursor: step index -> pointer to X[row rl][column 16 ks + g]
+  // load cursor: step index -> pointer to Xs[row rl][column 16 ks + g]
   int64_t lt = 0;
-  const double *lp = X + rl + (int64_t)g * ldx;
+  const double *lp = Xs + rl + (int64_t)g * ldxs;
   auto load = [&](double (&db)[4]) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) db[s] = lp[(int64_t)(4 * s) * ldx];
+    for (int s = 0; s < 4; ++s) db[s] = lp[(int64_t)(4 * s) * ldxs];
     if (lt + 1 < T) {  // advance; past the end the last step is re-read
       ++lt;
-      lp += ((lt % NK) == 0) ? rstep - (int64_t)(NK - 1) * 16 * ldx : 16 * ldx;
+      lp += ((lt % NK) == 0) ? rstep - (int64_t)(NK - 1) * 16 * ldxs : 16 * ldxs;
     }
   };
   double ring[4][4];
@@ -1096,10 +1098,10 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
   }
   if (!subtract && ncg != 1) return hipErrorInvalidValue;  // in-place needs one column group
   if (!subtract && upper_y && batch == 1 && p == q && (q == 64 || q == 128) &&
-      m >= kTrsmRows && L == C && Cin == C && ldl == ldc && ldy == q && (ldc % 2 == 0) &&
-      ((uintptr_t)C % 16 == 0) && (!C2 || ((ldc2 % 2 == 0) && ((uintptr_t)C2 % 16 == 0)))) {
-    // in-place Q = X U^{-1}: persistent U^{-1}-in-LDS kernel over the full
-    // row blocks, k_nn for the remaining rows
+      m >= kTrsmRows && Cin == C && (L == C || ldl >= m) && ldy == q && L2 == L) {
+    // Q = X U^{-1} (in place or from a separate X): persistent
+    // U^{-1}-in-LDS kernel over the full row blocks, k_nn for the remaining
+    // rows
     const int64_t mfull = m / kTrsmRows * kTrsmRows;  // > 0; the k_nn call below has m < 256
     {
       static bool attr = false;
@@ -1123,12 +1125,12 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
       const int64_t grid = std::min<int64_t>(nblk, std::max(cus, 1));
       if (q == 128)
         hipLaunchKernelGGL(k_trsm<128>, dim3((unsigned)grid), dim3(512),
-                           (size_t)q * q * sizeof(double), s, mfull, C, ldc, Y, ldy, C2, ldc2, info,
-                           skip);
+                           (size_t)q * q * sizeof(double), s, mfull, L, ldl, C, ldc, Y, ldy, C2,
+                           ldc2, info, skip);
       else
         hipLaunchKernelGGL(k_trsm<64>, dim3((unsigned)grid), dim3(512),
-                           (size_t)q * q * sizeof(double), s, mfull, C, ldc, Y, ldy, C2, ldc2, info,
-                           skip);
+                           (size_t)q * q * sizeof(double), s, mfull, L, ldl, C, ldc, Y, ldy, C2,
+                           ldc2, info, skip);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess || mfull == m) return e;
     }

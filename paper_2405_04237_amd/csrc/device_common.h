@@ -115,9 +115,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 // trailing upper triangle, each element's terms subtracted in column order
 // (the order of the unblocked right-looking algorithm). Returns 0 or the
 // 1-based column of the first pivot that is not > 0 (NaN included), the
-// same in every thread. `flag` is one int of LDS.
+// same in every thread. `flag` is one int of LDS; S needs 16 doubles of
+// scratch after the wp x wp matrix (the panel's pivot reciprocals).
 __device__ inline int lds_cholesky_blocked(double *S, int wp, int *flag) {
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+  double *rpiv = S + wp * wp;  // 16 doubles of scratch after the matrix
   if (tid == 0) *flag = 0;
   __syncthreads();
   for (int p0 = 0; p0 < wp; p0 += 16) {
@@ -144,6 +146,9 @@ __device__ inline int lds_cholesky_blocked(double *S, int wp, int *flag) {
         wave_lds_sync();
       }
     }
+    // the panel's pivot reciprocals (scratch after the matrix): the row
+    // solve multiplies by them, as LAPACK's unblocked Cholesky scales rows
+    if (tid < 16 && p0 + tid < wp) rpiv[tid] = 1.0 / S[(p0 + tid) * wp + p0 + tid];
     __syncthreads();
     const int fail = *flag;
     if (fail) return fail;
@@ -156,7 +161,7 @@ __device__ inline int lds_cholesky_blocked(double *S, int wp, int *flag) {
         const int j = c0 + e / 16, k = e % 16;
         double v = S[(p0 + k) * wp + j];
         for (int st = 0; st < 16; ++st) {
-          const double x = __shfl(v / S[(p0 + st) * wp + p0 + st], st, 16);
+          const double x = __shfl(v * rpiv[st], st, 16);
           if (k == st) v = x;
           if (k > st) v -= S[(p0 + st) * wp + p0 + k] * x;
         }
@@ -191,7 +196,7 @@ __device__ inline int lds_cholesky_blocked(double *S, int wp, int *flag) {
 // first every thread forms the right-hand sides of block row i from the
 // finished rows below (into tmp, 16 x wp), then one thread per column solves
 // with the 16 x 16 diagonal block (kept transposed in the block's strict
-// lower triangle, its diagonal in dg[16]). Each entry of X is thus a
+// lower triangle, the reciprocals of its diagonal in dg[16]). Each entry of X is thus a
 // substitution step of U X = I, so U X - I stays at the rounding level of
 // U's entries, which is what Q = A U^{-1} needs. The strict lower triangle
 // of S is overwritten.
@@ -202,7 +207,7 @@ __device__ inline void lds_upper_inverse_blocked(double *S, int wp, double *tmp,
     for (int e = tid; e < 16 * 16; e += nt) {  // U_ii^T below the diagonal, diagonal to dg
       const int r = e / 16, t = e % 16;
       if (t > r) S[(o + t) * wp + o + r] = S[(o + r) * wp + o + t];
-      if (t == r) dg[r] = S[(o + r) * wp + o + r];
+      if (t == r) dg[r] = 1.0 / S[(o + r) * wp + o + r];  // reciprocal of the pivot
     }
     for (int e = tid; e < 16 * ncols; e += nt) {
       const int r = e / ncols, j = o + e % ncols;
@@ -245,7 +250,7 @@ __device__ inline void lds_upper_inverse_blocked(double *S, int wp, double *tmp,
       const int j = o + e / 16, r = e % 16;
       double v = tmp[r * wp + j];
       for (int st = 15; st >= 0; --st) {
-        const double x = __shfl(v / dg[st], st, 16);
+        const double x = __shfl(v * dg[st], st, 16);
         if (r == st) v = x;
         if (r < st) v -= S[(o + st) * wp + o + r] * x;
       }

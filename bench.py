@@ -316,12 +316,28 @@ def bench_small_graph(steps: int):
     e1.record()
     torch.cuda.synchronize()
     graph = e0.elapsed_time(e1) / reps
+    # the same matrix through the persistent batched kernel: one launch (a
+    # team of workgroups), panel reductions in local memory
+    call = cqr.BatchedCall([a], bs=[b])
+    for _ in range(3):
+        call.launch()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        call.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    single = e0.elapsed_time(e1) / reps
     hf = householder_flops(m, n)
-    log(f"small single matrix: eager {eager:.3f} ms, graph {graph:.3f} ms")
+    log(f"small single matrix: eager {eager:.3f} ms, graph {graph:.3f} ms, "
+        f"single launch {single:.3f} ms")
     return {"workload": f"{m} x {n}, b = {b}, kappa=1e12", "reps": reps,
             "eager_ms": round(eager, 4), "graph_ms": round(graph, 4),
+            "single_launch_ms": round(single, 4),
             "eager_gflops_hh": round(hf / (eager * 1e-3) / 1e9, 1),
-            "graph_gflops_hh": round(hf / (graph * 1e-3) / 1e9, 1), "info": int(ws.info.item())}
+            "graph_gflops_hh": round(hf / (graph * 1e-3) / 1e9, 1),
+            "single_launch_gflops_hh": round(hf / (single * 1e-3) / 1e9, 1),
+            "info": int(ws.info.item()), "single_launch_info": int(call.info[0].item())}
 
 
 def cpu_baseline(w: dict, b: int, schedule: str, rows: int):
@@ -385,7 +401,7 @@ def main():
     import matgen
     import paper_2405_04237_amd as cqr
     from paper_2405_04237_amd import _lib, measure, tune
-    from paper_2405_04237_amd.costs import householder_flops
+    from paper_2405_04237_amd.costs import householder_flops, schedule_bytes, schedule_flops
 
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
@@ -474,6 +490,17 @@ def main():
         res = measure.residual(a, q, r)
         log(f"orthogonality {orth:.3e}  residual {res:.3e}  info {info}")
     value = householder_flops(m, n) / (ms * 1e-3) / 1e9
+    # the whole step against both peaks: the flops the schedule executes
+    # (about twice the Householder count, so value tops out near half of
+    # the FP64 peak) and its compulsory bytes (each operand of each
+    # streaming step read once, each output written once)
+    ex_fl = schedule_flops(m, n, b, args.schedule)
+    ex_by = schedule_bytes(m, n, b, args.schedule)
+    step_roof = {"executed_tflops": round(ex_fl / (ms * 1e-3) / 1e12, 2),
+                 "frac_fp64_peak": round(ex_fl / (ms * 1e-3) / PEAK_FP64, 4),
+                 "algorithmic_gbs": round(ex_by / (ms * 1e-3) / 1e9, 1),
+                 "frac_hbm_peak": round(ex_by / (ms * 1e-3) / PEAK_HBM, 4),
+                 "executed_over_householder": round(ex_fl / householder_flops(m, n), 3)}
     staged = None
     if args.lda_pad and not args.no_staged:
         # the same matrix stored with lda = m: the library factors a staging copy
@@ -507,7 +534,8 @@ def main():
                    "kappa": kappa if args.input == "kappa" else None, "input": args.input, "b": b,
                    "schedule": "mCQR2GS" if args.schedule == "mod" else "CQR2GS"},
         "orthogonality": orth, "orthogonality_normalised": None if orth is None else orth / math.sqrt(n), "residual": res,
-        "info": info, "wall_s": round(wall, 3), "roofline": roof, "kernels": kern,
+        "info": info, "wall_s": round(wall, 3), "roofline": roof, "step_roofline": step_roof,
+        "kernels": kern,
         "tune": table, "lda_m": staged,
     }
     del q, r, ws, a

@@ -537,6 +537,14 @@ def main():
         "info": info, "wall_s": round(wall, 3), "roofline": roof, "step_roofline": step_roof,
         "kernels": kern,
         "tune": table, "lda_m": staged,
+        "paper_context": {
+            "note": "the paper's own figures, other hardware and shapes, with communication; "
+                    "context only, not this metric's baseline",
+            "speedup_over_scalapack_pdgeqrf": {"cpu_version": ">6x", "gpu_version": "80x",
+                                               "workload": "weak scaling, 10000 x 3000 rows per rank"},
+            "gpu_hardware": "NVIDIA A100 40 GB, 4 per node (1 to 12 nodes)",
+            "mcqr2gs_gpu_1_node_ms": 71.78,
+            "householder_equivalent_tflops_per_a100": 2.44},
     }
     del q, r, ws, a
     torch.cuda.empty_cache()

@@ -63,10 +63,14 @@ def test_cfg1_shape_against_oracle(sched, kappa):
 
 @pytest.mark.parametrize("sched", ["orig", "mod"])
 @pytest.mark.parametrize("m,n,b,ld", [(1000, 40, 16, 1000), (1000, 40, 16, 1013), (777, 77, 13, 800),
-                                      (70000, 130, 64, 70001), (5000, 1, 1, 5000)])
+                                      (70000, 130, 64, 70001), (5000, 1, 1, 5000),
+                                      (20000, 300, 128, 20000), (128, 128, 64, 128),
+                                      (130, 128, 128, 131)])
 def test_ragged_shapes(sched, m, n, b, ld):
     """Row counts off the 16/64-row tiles, odd leading dimensions (scalar
-    loads), ragged last panels, n = 1."""
+    loads), ragged last panels (also after 128-column panels), n = 1, a
+    square matrix, and m just above n (one 128-row block of Q = X U^{-1}
+    plus a two-row tail)."""
     kappa = 1e8
     a = matgen.test_matrix(m, n, kappa, seed=3)
     q, r = _factor(a, b, sched, ld=ld)

@@ -675,19 +675,24 @@ size_t batched_lds_bytes() {
   return (size_t)(kYSize + 4 * kBB + 64 + kBB + kBatchMaxPanel) * sizeof(double) + 64;
 }
 
+// The kernel's dynamic LDS limit, raised once per process (a function-local
+// static is initialised once and thread-safely) before it is launched or its
+// occupancy is queried.
+static hipError_t batched_lds_attr() {
+  static const hipError_t attr =
+      hipFuncSetAttribute((const void *)k_batched_mod, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)batched_lds_bytes());
+  return attr;
+}
+
 hipError_t launch_batched_mod(int grid, const BatchSlot *slots, int nslots, const int64_t *ms,
                               const int *ns, const int *bs, const double *const *dA,
                               const int64_t *dlda, double *const *dQ, double *const *dR,
                               int *dinfo, int *queue, double *team_part, int *team_cnt, int nteams,
                               hipStream_t s) {
-  static bool attr_set = false;
   const size_t lds = batched_lds_bytes();
-  if (!attr_set) {
-    const hipError_t e = hipFuncSetAttribute((const void *)k_batched_mod,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  const hipError_t attr = batched_lds_attr();
+  if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL(k_reset_batched, dim3(1), dim3(256), 0, s, queue, team_cnt, nteams);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -697,6 +702,7 @@ hipError_t launch_batched_mod(int grid, const BatchSlot *slots, int nslots, cons
 }
 
 int batched_blocks_per_cu() {
+  if (batched_lds_attr() != hipSuccess) return 1;
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_batched_mod, kThreads,
                                                    batched_lds_bytes()) != hipSuccess)

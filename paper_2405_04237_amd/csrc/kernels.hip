@@ -1046,6 +1046,16 @@ __global__ __launch_bounds__(512, 1) void k_nn_ys(int64_t m, int p, int q, const
 // rows of C per workgroup row-slab is 16 * RB * WR
 constexpr int kNnRB = 2;
 
+// CU count of the device current at the first call (one-time set-up through
+// function-local statics, which C++ initialises once and thread-safely).
+static int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 256;
+  return cus > 0 ? cus : 256;
+}
+
 hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const double *L,
                      int64_t ldl, const double *Y, int64_t ldy, const double *Cin, int64_t ldci,
                      double *C, int64_t ldc, const int *info, hipStream_t s, const double *L2,
@@ -1073,20 +1083,11 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
       (sL2 % 2 == 0) && (sC % 2 == 0)) {
     // no input C, inner dimension <= 256: Y staged in LDS, one 8-wave
     // workgroup per CU, rows shared equally among a slab's workgroups
-    static bool attr = false;
-    static int cus = 0;
-    if (!attr) {
-      hipError_t e = hipFuncSetAttribute((const void *)k_nn_ys,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         kYsMaxK * kTile * (int)sizeof(double));
-      if (e != hipSuccess) return e;
-      int dev = 0;
-      e = hipGetDevice(&dev);
-      if (e != hipSuccess) return e;
-      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-      if (e != hipSuccess) return e;
-      attr = true;
-    }
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)k_nn_ys, hipFuncAttributeMaxDynamicSharedMemorySize,
+        kYsMaxK * kTile * (int)sizeof(double));
+    if (attr != hipSuccess) return attr;
+    static const int cus = device_cus();
     const int64_t per = std::max<int64_t>(1, (int64_t)std::max(cus, 1) / ((int64_t)slabs * batch));
     int64_t rpw = (m + per - 1) / per;
     rpw = (rpw + 31) / 32 * 32;
@@ -1104,23 +1105,17 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
     // rows
     const int64_t mfull = m / kTrsmRows * kTrsmRows;  // > 0; the k_nn call below has m < 256
     {
-      static bool attr = false;
-      static int cus = 0;
-      if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_trsm<128>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           kMaxPanel * kMaxPanel * (int)sizeof(double));
+      static const hipError_t attr = [] {
+        const hipError_t e = hipFuncSetAttribute((const void *)k_trsm<128>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 kMaxPanel * kMaxPanel * (int)sizeof(double));
         if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void *)k_trsm<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                64 * 64 * (int)sizeof(double));
-        if (e != hipSuccess) return e;
-        int dev = 0;
-        e = hipGetDevice(&dev);
-        if (e != hipSuccess) return e;
-        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) return e;
-        attr = true;
-      }
+        return hipFuncSetAttribute((const void *)k_trsm<64>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   64 * 64 * (int)sizeof(double));
+      }();
+      if (attr != hipSuccess) return attr;
+      static const int cus = device_cus();
       const int64_t nblk = mfull / kTrsmRows;
       const int64_t grid = std::min<int64_t>(nblk, std::max(cus, 1));
       if (q == 128)
@@ -1141,20 +1136,11 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
   if (subtract && batch == 1 && psplit == p && nn_short_k(p, L, ldl, Cin, ldci, C, ldc)) {
     // one round of resident workgroups (two per CU): each slab gets an equal
     // share of them, each with an equal range of rows (a multiple of 32)
-    static bool attr = false;
-    static int cus = 0;
-    if (!attr) {
-      hipError_t e = hipFuncSetAttribute((const void *)k_upd,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         kUpdMaxK * kTile * (int)sizeof(double));
-      if (e != hipSuccess) return e;
-      int dev = 0;
-      e = hipGetDevice(&dev);
-      if (e != hipSuccess) return e;
-      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-      if (e != hipSuccess) return e;
-      attr = true;
-    }
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)k_upd, hipFuncAttributeMaxDynamicSharedMemorySize,
+        kUpdMaxK * kTile * (int)sizeof(double));
+    if (attr != hipSuccess) return attr;
+    static const int cus = device_cus();
     const int64_t per_slab = std::max<int64_t>(1, 2 * (int64_t)std::max(cus, 1) / slabs);
     int64_t rpw = (m + per_slab - 1) / per_slab;
     rpw = (rpw + 31) / 32 * 32;
@@ -1389,14 +1375,10 @@ hipError_t launch_chol_inv(const double *W, int w, double *uout, double *rblk, i
   if (w < 1 || w > kMaxPanel) return hipErrorInvalidValue;
   const int wp = blocked_order(w);
   const size_t lds = (size_t)blocked_lds_doubles(wp) * sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set) {
-    const size_t most = (size_t)blocked_lds_doubles(kMaxPanel) * sizeof(double);
-    const hipError_t e = hipFuncSetAttribute((const void *)k_chol_inv,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)most);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  static const hipError_t attr = hipFuncSetAttribute(
+      (const void *)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
+      (int)((size_t)blocked_lds_doubles(kMaxPanel) * sizeof(double)));
+  if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kCholThreads), lds, s, W, w, uout, rblk, ldr, uinv,
                      info, col0, skip_tol, skip);
   return hipGetLastError();
@@ -1432,14 +1414,10 @@ hipError_t launch_tri_inv(const double *R, int n, int64_t sR, double *Rinv, int6
   if (n < 1 || n > kMaxPanel) return hipErrorInvalidValue;
   const int wp = blocked_order(n);
   const size_t lds = (size_t)blocked_lds_doubles(wp) * sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set) {
-    const size_t most = (size_t)blocked_lds_doubles(kMaxPanel) * sizeof(double);
-    const hipError_t e = hipFuncSetAttribute((const void *)k_tri_inv,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)most);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  static const hipError_t attr = hipFuncSetAttribute(
+      (const void *)k_tri_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
+      (int)((size_t)blocked_lds_doubles(kMaxPanel) * sizeof(double)));
+  if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL(k_tri_inv, dim3((unsigned)batch), dim3(kCholThreads), lds, s, R, n, sR, Rinv,
                      sRi);
   return hipGetLastError();

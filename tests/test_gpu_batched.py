@@ -131,3 +131,17 @@ def test_batched_teams_breakdown_and_determinism():
     for i in (0, 2, 3, 4, 5, 6, 7):
         assert np.array_equal(q1[i], q2[i]) and np.array_equal(r1[i], r2[i])
         _check(mats[i], q1[i], r1[i], specs[i][2], specs[i][3])
+
+
+def test_batched_short_and_square():
+    """Matrices far below the workload's 2048 rows: square (m = n = 128 and
+    64), m just above n, a ragged panel width, and one narrow matrix, all in
+    one launch (one workgroup each; no row-split team below 4096 rows)."""
+    specs = [(128, 128, 32, 1e6), (200, 100, 25, 1e8), (64, 64, 16, 1e3), (1000, 7, 3, 1e2),
+             (130, 128, 32, 1e10)]
+    mats = [matgen.test_matrix(m, n, k, seed=900 + i) for i, (m, n, b, k) in enumerate(specs)]
+    qs, rs, info = cqr.qr_batched([to_dev(a) for a in mats], bs=[s[2] for s in specs])
+    torch.cuda.synchronize()
+    assert not info.any()
+    for a, q, r, (m, n, b, k) in zip(mats, qs, rs, specs):
+        _check(a, to_host(q), to_host(r), b, k)

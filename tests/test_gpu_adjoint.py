@@ -156,3 +156,27 @@ def test_cfg5_full_size():
     fd = (_loss(to_dev(a + h * e), dq, dr) - _loss(to_dev(a - h * e), dq, dr)) / (2 * h)
     exact = float(np.sum(got * e))
     assert abs(fd - exact) <= 1e-3 * abs(exact)
+
+
+def test_adjoint_batched_n128_against_oracle():
+    """4 x (8192 x 128), kappa = 1e3: the batched first pass of a 128-column
+    adjoint (two balanced waves per row chunk, one matrix per grid row)
+    against the oracle and per-matrix calls."""
+    bsz, m, n, kappa = 4, 8192, 128, 1e3
+    qs, rs, dqs, drs = [], [], [], []
+    for i in range(bsz):
+        a = matgen.test_matrix(m, n, kappa, seed=300 + i)
+        q, r = oracle.mcqr2gs(a, 32)
+        dq, dr = matgen.cotangents(m, n, seed=300 + i)
+        qs.append(q), rs.append(r), dqs.append(dq), drs.append(dr)
+
+    def stack(ms):
+        return torch.from_numpy(np.stack([np.ascontiguousarray(x.T) for x in ms])).to("cuda").transpose(1, 2)
+
+    da = cag.qr_backward_batched(stack(rs), dq=stack(dqs), dr=stack(drs), q=stack(qs))
+    torch.cuda.synchronize()
+    for i in range(bsz):
+        got = np.asfortranarray(da[i].cpu().numpy())
+        ref = oracle.qr_adjoint(qs[i], rs[i], dqs[i], drs[i])
+        assert oracle.rel_fro(got, ref) <= 100 * n * U * kappa
+        assert oracle.rel_fro(got, _bwd(qs[i], rs[i], dqs[i], drs[i])) <= 100 * n * U * kappa

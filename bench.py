@@ -188,7 +188,7 @@ def bench_scqr3(steps: int, warmup: int):
     r = cqr.empty_colmajor(n, n, dev)
     out = {"workload": f"{m} x {n}, kappa={kappa:.0e}, lda {m + 16}"}
     for sched, b in (("scqr3", 0), ("mod", 32)):
-        ws = cqr.Workspace(m, n, b, sched, dev)
+        ws = cqr.Workspace(m, n, b, sched, dev, lda=a.stride(1))
 
         def step():
             cqr.qr(a, b=b, schedule=sched, out=(q, r), workspace=ws, check=False)
@@ -244,7 +244,7 @@ def bench_adaptive(steps: int, warmup: int):
         a = matgen.test_matrix_device(m, n, kappa, seed=61, device=dev, ld=m + 16)
         q = cqr.empty_colmajor(m, n, dev, ld=a.stride(1))
         r = cqr.empty_colmajor(n, n, dev)
-        ws = cqr.Workspace(m, n, b, "mod", dev)
+        ws = cqr.Workspace(m, n, b, "mod", dev, lda=a.stride(1))
         res = {}
         for mode in (False, True):
             def step():
@@ -340,6 +340,143 @@ def bench_small_graph(steps: int):
             "info": int(ws.info.item()), "single_launch_info": int(call.info[0].item())}
 
 
+def time_steps(torch, step, steps: int, stream):
+    """Run `steps` steps back to back between two synchronisations, with a
+    HIP event on `stream` between consecutive steps: mean (total time /
+    steps, the paper's statistic) and median of the per-step times."""
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    evs[0].record(stream)
+    for i in range(steps):
+        step()
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+    srt = sorted(per)
+    med = srt[steps // 2] if steps % 2 else 0.5 * (srt[steps // 2 - 1] + srt[steps // 2])
+    return {"mean_ms": evs[0].elapsed_time(evs[steps]) / steps, "median_ms": med,
+            "min_ms": srt[0], "max_ms": srt[-1]}
+
+
+def kernel_table(_lib, steps: int):
+    """Per-class launches, time and rates from the library's HIP-event
+    bracketing (cqr_profile_*), per step."""
+    kern = {}
+    for kind in _lib.KERNEL_KINDS:
+        p = _lib.profile_query(kind)
+        if p["launches"]:
+            kern[kind] = {"launches_per_step": p["launches"] / steps,
+                          "ms_per_step": p["ms"] / steps,
+                          "avg_launch_us": 1e3 * p["ms"] / p["launches"],
+                          "tflops": p["flops"] / (p["ms"] * 1e-3) / 1e12 if p["ms"] else 0.0,
+                          "gbs": p["bytes"] / (p["ms"] * 1e-3) / 1e9 if p["ms"] else 0.0,
+                          "flops_per_launch": p["flops"] / p["launches"],
+                          "bytes_per_launch": p["bytes"] / p["launches"]}
+    return kern
+
+
+def bench_tsqr_legs(steps: int, warmup: int):
+    """The two smaller single-matrix workloads under both panel schedules,
+    each beside the oracle on the host:
+    * 2^20 x 256, b = 64, kappa in {1e5, 1e10, 1e15} (HBM-bound: about 3.2e10
+      bytes of compulsory traffic per factorisation);
+    * 4096 x 64, b = 16, kappa = 1e12 (latency-bound: ~70 dependent launches),
+      eager and as one HIP graph replay."""
+    import numpy as np
+    import torch
+    import matgen
+    import oracle
+    import paper_2405_04237_amd as cqr
+    from paper_2405_04237_amd import measure
+    from paper_2405_04237_amd.costs import householder_flops, schedule_bytes, schedule_flops
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    m, n, b = 1 << 20, 256, 64
+    for kappa in (1e5, 1e10, 1e15):
+        a = matgen.test_matrix_device(m, n, kappa, seed=2, device=dev, ld=m + 16)
+        q = cqr.empty_colmajor(m, n, dev, ld=a.stride(1))
+        r = cqr.empty_colmajor(n, n, dev)
+        # the oracle on a row sample of the same recipe (2^18 rows)
+        ah = matgen.test_matrix(1 << 18, n, kappa, seed=2)
+        for sched in ("orig", "mod"):
+            ws = cqr.Workspace(m, n, b, sched, dev, lda=a.stride(1))
+
+            def step():
+                cqr.qr(a, b=b, schedule=sched, out=(q, r), workspace=ws, check=False)
+
+            for _ in range(warmup):
+                step()
+            tm = time_steps(torch, step, steps, stream)
+            ms = tm["mean_ms"]
+            by = schedule_bytes(m, n, b, sched)
+            fo = oracle.mcqr2gs if sched == "mod" else oracle.cqr2gs
+            t0 = time.perf_counter()
+            fo(ah, b)
+            to = time.perf_counter() - t0
+            res = {"ms": round(ms, 4), "median_ms": round(tm["median_ms"], 4),
+                   "value": round(householder_flops(m, n) / (ms * 1e-3) / 1e9, 1),
+                   "unit": "GFLOP/s", "info": int(ws.info.item()),
+                   "orthogonality": measure.orthogonality(q), "residual": measure.residual(a, q, r),
+                   "executed_tflops": round(schedule_flops(m, n, b, sched) / (ms * 1e-3) / 1e12, 2),
+                   "roofline": {"bound": "hbm", "achieved": round(by / (ms * 1e-3) / 1e9, 1),
+                                "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                                "frac": round(by / (ms * 1e-3) / PEAK_HBM, 4),
+                                "bytes_model": "compulsory bytes of every streaming step"},
+                   "oracle": {"rows": 1 << 18, "s": round(to, 3),
+                              "value": round(householder_flops(1 << 18, n) / to / 1e9, 2),
+                              "unit": "GFLOP/s"}}
+            out[f"2^20x256 {sched} kappa={kappa:.0e}"] = res
+            log(f"2^20x256 {sched} kappa {kappa:.0e}: {ms:.3f} ms (median {tm['median_ms']:.3f}), "
+                f"orthogonality {res['orthogonality']:.2e}, oracle {to:.2f} s on 2^18 rows")
+            del ws
+        del a, q, r, ah
+    torch.cuda.empty_cache()
+    m, n, b, kappa = 4096, 64, 16, 1e12
+    a = matgen.test_matrix_device(m, n, kappa, seed=1, device=dev)
+    ah = matgen.test_matrix(m, n, kappa, seed=1)
+    q = cqr.empty_colmajor(m, n, dev, ld=a.stride(1))
+    r = cqr.empty_colmajor(n, n, dev)
+    reps = max(steps, 50)
+    for sched in ("orig", "mod"):
+        ws = cqr.Workspace(m, n, b, sched, dev, lda=a.stride(1))
+
+        def step():
+            cqr.qr(a, b=b, schedule=sched, out=(q, r), workspace=ws, check=False)
+
+        for _ in range(3):
+            step()
+        eager = time_steps(torch, step, reps, stream)
+        g = torch.cuda.CUDAGraph()
+        s2 = torch.cuda.Stream()
+        s2.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s2):
+            with torch.cuda.graph(g, stream=s2):
+                step()
+        torch.cuda.current_stream().wait_stream(s2)
+        for _ in range(3):
+            g.replay()
+        graph = time_steps(torch, g.replay, reps, stream)
+        fo = oracle.mcqr2gs if sched == "mod" else oracle.cqr2gs
+        ts = []
+        for _ in range(10):
+            t0 = time.perf_counter()
+            fo(ah, b)
+            ts.append(time.perf_counter() - t0)
+        hf = householder_flops(m, n)
+        out[f"4096x64 {sched} kappa=1e12"] = {
+            "eager_ms": round(eager["mean_ms"], 4), "eager_median_ms": round(eager["median_ms"], 4),
+            "graph_ms": round(graph["mean_ms"], 4), "graph_median_ms": round(graph["median_ms"], 4),
+            "value_graph": round(hf / (graph["mean_ms"] * 1e-3) / 1e9, 1), "unit": "GFLOP/s",
+            "info": int(ws.info.item()), "orthogonality": measure.orthogonality(q),
+            "oracle": {"mean_s": round(sum(ts) / len(ts), 5), "median_s": round(sorted(ts)[5], 5)}}
+        log(f"4096x64 {sched}: eager {eager['mean_ms']:.3f} ms, graph {graph['mean_ms']:.3f} ms, "
+            f"oracle {sum(ts) / len(ts) * 1e3:.2f} ms")
+        del ws, g
+    return out
+
+
 def cpu_baseline(w: dict, b: int, schedule: str, rows: int):
     """The oracle, untuned, on a row sample of the workload (host cores)."""
     import numpy as np
@@ -429,7 +566,7 @@ def main():
         if b is None:
             log("no candidate panel width met the accuracy gate; using the narrowest")
             b = min(w["b_cands"])
-    ws = cqr.Workspace(m, n, b, args.schedule, dev)
+    ws = cqr.Workspace(m, n, b, args.schedule, dev, lda=a.stride(1))
     q = cqr.empty_colmajor(m, n, dev, ld=a.stride(1))
     r = cqr.empty_colmajor(n, n, dev)
     stream = torch.cuda.current_stream(dev)
@@ -437,39 +574,37 @@ def main():
     def step():
         cqr.qr(a, b=b, schedule=args.schedule, out=(q, r), workspace=ws, check=False)
 
+    # warmup with every kernel class bracketed by HIP events: the per-kernel
+    # table, and which class dominates the step
+    _lib.profile_select(None)
+    _lib.profile_reset()
+    _lib.profile_enable(True)
+    args.warmup = max(1, args.warmup)
     for i in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps), timing {args.steps} steps at b={b}")
-    _lib.profile_reset()
-    _lib.profile_enable(True)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for i in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     _lib.profile_enable(False)
-    ms = ev0.elapsed_time(ev1) / args.steps
-    info = int(ws.info.item())
-    kern = {}
-    for kind in _lib.KERNEL_KINDS:
-        p = _lib.profile_query(kind)
-        if p["launches"]:
-            kern[kind] = {"launches_per_step": p["launches"] / args.steps,
-                          "ms_per_step": p["ms"] / args.steps,
-                          "avg_launch_us": 1e3 * p["ms"] / p["launches"],
-                          "tflops": p["flops"] / (p["ms"] * 1e-3) / 1e12 if p["ms"] else 0.0,
-                          "gbs": p["bytes"] / (p["ms"] * 1e-3) / 1e9 if p["ms"] else 0.0,
-                          "flops_per_launch": p["flops"] / p["launches"],
-                          "bytes_per_launch": p["bytes"] / p["launches"]}
-    log("per-kernel: " + json.dumps({k: {kk: round(vv, 3) for kk, vv in v.items()}
-                                      for k, v in kern.items()}))
+    kern = kernel_table(_lib, args.warmup)
+    log("per-kernel (warmup): " + json.dumps({k: {kk: round(vv, 3) for kk, vv in v.items()}
+                                               for k, v in kern.items()}))
     dom = max((k for k in kern if k in ("gram", "proj", "update", "update_long", "trsm")),
               key=lambda k: kern[k]["ms_per_step"])
+    # the timed region: only the dominant class carries events (two records
+    # per launch of it), so the step time is that of the plain library
+    log(f"warmup done ({args.warmup} steps), timing {args.steps} steps at b={b}")
+    _lib.profile_select([dom])
+    _lib.profile_reset()
+    _lib.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tm = time_steps(torch, step, args.steps, stream)
+    wall = time.perf_counter() - t0
+    _lib.profile_enable(False)
+    _lib.profile_select(None)
+    ms = tm["mean_ms"]
+    info = int(ws.info.item())
+    live = kernel_table(_lib, args.steps)
+    kern[dom] = live[dom]
     kd = kern[dom]
     intensity = kd["flops_per_launch"] / kd["bytes_per_launch"]
     if intensity >= PEAK_FP64 / PEAK_HBM:
@@ -508,7 +643,7 @@ def main():
         a2.copy_(a)
         del q
         q = cqr.empty_colmajor(m, n, dev, ld=m)
-        ws2 = cqr.Workspace(m, n, b, args.schedule, dev)
+        ws2 = cqr.Workspace(m, n, b, args.schedule, dev, lda=a2.stride(1))
         k2 = max(1, min(args.steps, 3))
         for i in range(1 + k2):
             if i == 1:
@@ -528,6 +663,8 @@ def main():
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "median_ms_per_step": round(tm["median_ms"], 3),
+        "step_ms_range": [round(tm["min_ms"], 3), round(tm["max_ms"], 3)],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "lda": lda,
@@ -535,7 +672,7 @@ def main():
                    "schedule": "mCQR2GS" if args.schedule == "mod" else "CQR2GS"},
         "orthogonality": orth, "orthogonality_normalised": None if orth is None else orth / math.sqrt(n), "residual": res,
         "info": info, "wall_s": round(wall, 3), "roofline": roof, "step_roofline": step_roof,
-        "kernels": kern,
+        "kernels": kern, "kernels_note": "per-class HIP-event times from the warmup steps, except the roofline kernel (timed region)",
         "tune": table, "lda_m": staged,
         "paper_context": {
             "note": "the paper's own figures, other hardware and shapes, with communication; "
@@ -556,6 +693,7 @@ def main():
         out["scqr3"] = bench_scqr3(max(args.steps, 5), 2)
         out["adaptive"] = bench_adaptive(max(args.steps, 5), 2)
         out["small_graph"] = bench_small_graph(args.steps)
+        out["tsqr_legs"] = bench_tsqr_legs(max(args.steps, 10), 3)
     if args.calibration_copy:
         x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         y = torch.ones(1 << 27, dtype=torch.float64, device=dev)

@@ -121,8 +121,19 @@ typedef struct cqr_options {
 
 /* Factor A = Q R with the default schedule (mCQR2GS). Q has leading
  * dimension lda, R leading dimension n. Uses the library's internal
- * workspace and info word, so concurrent calls on different streams of one
- * device must use cqr_factor_ex with their own workspace instead. */
+ * workspace and info word (read the info word with cqr_get_info), so
+ * concurrent calls on different streams of one device must use
+ * cqr_factor_ex with their own workspace instead.
+ *
+ * The internal workspace is allocated by the first call on a device and
+ * grown, when a later call needs more, in stream order on `stream`: that
+ * stream waits (an event, not the host) for the last call that used the old
+ * buffer, which is then released with hipFreeAsync, and the new buffer comes
+ * from hipMallocAsync. The host never waits for the device. A call made
+ * while `stream` is being captured into a graph must not use the internal
+ * workspace (it returns CQR_ERR_ARG: pass a workspace to cqr_factor_ex), and
+ * the first call on a device, which allocates the info word, must not be
+ * captured. */
 int cqr_factor(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
                double *Q, double *R, void *stream);
 
@@ -131,8 +142,17 @@ int cqr_factor(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
 int cqr_factor_ex(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
                   double *Q, double *R, void *stream, const cqr_options *opt);
 
-/* Bytes of device workspace cqr_factor_ex needs for these sizes (host
- * arithmetic only; 0 for invalid sizes). The info word is not included. */
+/* Bytes of device workspace cqr_factor_ex needs for these sizes and leading
+ * dimension (host arithmetic only; 0 for invalid sizes, lda < m included).
+ * The info word is not included. When lda is a multiple of 1024 doubles the
+ * column lines the split-m products read at one row share a few cache sets;
+ * such a call factors a copy with a shifted stride, and the workspace
+ * includes room for it (lda * n doubles). A caller workspace without that
+ * room (at least the size for a non-aliasing lda) is accepted, and the call
+ * then factors in place at the aliasing stride (same results, slower). */
+size_t cqr_workspace_bytes_ld(int64_t m, int64_t n, int64_t b, int64_t lda, int schedule);
+
+/* cqr_workspace_bytes_ld with lda = m (a tightly packed matrix). */
 size_t cqr_workspace_bytes(int64_t m, int64_t n, int64_t b, int schedule);
 
 /* Panel width used when b = 0 is passed (n for CQR_SCHED_SCQR3, which has
@@ -193,7 +213,9 @@ void cqr_plan_destroy(cqr_batch_plan *plan);
  * the strict lower triangle of dR is ignored. dA must not overlap any input.
  * 1 <= n <= CQR_MAX_PANEL (R^{-1} is formed in one workgroup's LDS).
  * workspace: >= cqr_backward_workspace_bytes(m, n, batch) bytes of device
- * memory, 256-byte aligned, or NULL for a buffer the library keeps per device.
+ * memory, 256-byte aligned, or NULL for a buffer the library keeps per device
+ * (grown in stream order as cqr_factor's workspace; a call during stream
+ * capture must pass its own and otherwise returns CQR_ERR_ARG).
  * Asynchronous on `stream`; bitwise reproducible. R^{-1} is computed on a
  * library-owned side stream of default priority, forked from and joined back
  * into `stream` with events, so it overlaps the first pass (a graph capture
@@ -242,6 +264,10 @@ enum cqr_kernel_kind {
   CQR_K_COUNT = 10
 };
 int cqr_profile_enable(int on);
+/* Restrict the bracketing to the kernel classes whose bit (1u << kind) is
+ * set in kind_mask (default: all), so that a timed run can carry events
+ * around one class only. */
+int cqr_profile_select(unsigned kind_mask);
 int cqr_profile_reset(void);
 int cqr_profile_query(int kind, int64_t *launches, double *ms, double *flops,
                       double *bytes);

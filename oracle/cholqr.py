@@ -161,20 +161,27 @@ def _panels(n: int, b: int):
 
 
 def cqrgs(a: np.ndarray, b: int):
-    """CholeskyQR with block Gram-Schmidt, Algorithm 6 (distributed form:
-    Algorithm 8). Returns Q, R. A is not modified."""
+    """CholeskyQR with block Gram-Schmidt (Algorithm 6; its distributed form
+    is Algorithm 8). Returns Q, R; A is not modified.
+
+    Left to right over the panels: CholeskyQR of the panel (its Gram matrix,
+    the Cholesky factor, which becomes the diagonal block of R, and the
+    triangular solve for the panel's Q), then one block classical
+    Gram-Schmidt step that removes the new Q panel from every column to its
+    right and records the coefficients as that block row of R.
+    """
     m, n = a.shape
     x = np.array(a, dtype=np.float64, order="F", copy=True)
     r = np.zeros((n, n))
     for (s, e) in _panels(n, b):
-        w = gram(x[:, s:e])                      # W_j := A_j^T A_j
-        u = chol_upper(w, s)                     # W_j = U^T U
-        x[:, s:e] = _right_solve_upper(x[:, s:e], u)   # Q_j := A_j U^{-1}
-        r[s:e, s:e] = u                          # R_jj := U
+        panel = x[:, s:e]
+        u = chol_upper(gram(panel), s)
+        x[:, s:e] = _right_solve_upper(panel, u)
+        r[s:e, s:e] = u
         if e < n:
-            y = xprod(x[:, s:e], x[:, e:])       # Y := Q_j^T A_{j+1:k}
-            x[:, e:] -= x[:, s:e] @ y            # A_{j+1:k} -= Q_j Y
-            r[s:e, e:] = y                       # R_{j,j+1:k} := Y
+            coef = xprod(x[:, s:e], x[:, e:])
+            x[:, e:] -= x[:, s:e] @ coef
+            r[s:e, e:] = coef
     return x, r
 
 
@@ -208,15 +215,16 @@ def _cqr_again(x: np.ndarray, col0: int, tol):
 def mcqr2gs(a: np.ndarray, b: int, adaptive=None):
     """Modified CholeskyQR2 with Gram-Schmidt (mCQR2GS), Algorithm 9.
 
-    Steps per panel j >= 2 (1-based as in the paper):
-      Y := Q_{j-1}^T A_{:,j:k};  A_{:,j:k} -= Q_{j-1} Y;  R_{j-1,j:k} := Y
-      CQR of panel j:     A_j = Qt Ua
-      re-orthogonalise:   Z := Q_{1:j-1}^T Qt;  Qt -= Q_{1:j-1} Z
-      CQR again:          Qt = Q_j Ub
-    so that A_j (after the Y updates) = Q_{1:j-1} (Z Ua) + Q_j (Ub Ua), which
-    gives R_{1:j-1,j} += Z Ua and R_jj = Ub Ua. The first panel is CQR2
-    (Algorithm 9, first line). The paper does not write R for this algorithm;
-    this is the bookkeeping that makes A = Q R hold.
+    The first panel gets CholeskyQR2. Every later panel first loses its
+    component along the previous (already final) panel, through a projection
+    of all columns to the right of that panel; it is then factored by
+    CholeskyQR (factor Ua), re-orthogonalised once against all finished
+    panels (coefficients Z), and factored by CholeskyQR again (factor Ub).
+    The projected panel therefore equals Q_{1:j-1} (Z Ua) + Q_j (Ub Ua):
+    R_{1:j-1,j} gains Z Ua and R_jj = Ub Ua, while the projection
+    coefficients fill the previous panel's block row. The paper does not
+    write R for this algorithm; this is the bookkeeping that makes A = Q R
+    hold.
 
     adaptive = tol (the run-time choice of repetitions the paper proposes in
     its conclusion): a repeated CholeskyQR is left out when the Gram matrix
@@ -238,15 +246,18 @@ def mcqr2gs(a: np.ndarray, b: int, adaptive=None):
     for jj in range(1, len(pan)):
         ps, pe = pan[jj - 1]
         s, e = pan[jj]
-        y = xprod(x[:, ps:pe], x[:, s:])          # Y := Q_{j-1}^T A_{:,j:k}
-        x[:, s:] -= x[:, ps:pe] @ y               # A_{:,j:k} -= Q_{j-1} Y
-        r[ps:pe, s:] = y                          # R_{j-1,j:k} := Y
-        qt, ua = cqr(x[:, s:e], s)                # CQR(A_j)
-        z = xprod(x[:, :s], qt)                   # Q_{1:j-1}^T A_j
+        # project the finished previous panel out of everything to its right
+        coef = xprod(x[:, ps:pe], x[:, s:])
+        x[:, s:] -= x[:, ps:pe] @ coef
+        r[ps:pe, s:] = coef
+        # first CholeskyQR of the new panel, then one classical Gram-Schmidt
+        # pass against all finished panels, then CholeskyQR again
+        qt, ua = cqr(x[:, s:e], s)
+        z = xprod(x[:, :s], qt)
         if adaptive is not None and np.linalg.norm(z) <= adaptive:
-            z = np.zeros_like(z)                  # orthogonal enough: no update
-        qt = qt - x[:, :s] @ z                    # A_j -= Q_{1:j-1} Q_{1:j-1}^T A_j
-        qj, ub = _cqr_again(qt, s, adaptive)      # Q_j = CQR(A_j)
+            z = np.zeros_like(z)
+        qt = qt - x[:, :s] @ z
+        qj, ub = _cqr_again(qt, s, adaptive)
         x[:, s:e] = qj
         r[:s, s:e] += z @ ua
         r[s:e, s:e] = ub @ ua

@@ -58,12 +58,13 @@ def _check_input(a):
 
 
 class Workspace:
-    """Device scratch and info word for repeated factorisations of one size."""
+    """Device scratch and info word for repeated factorisations of one size
+    and leading dimension (lda = m when not given)."""
 
-    def __init__(self, m: int, n: int, b: int, schedule: str, device):
+    def __init__(self, m: int, n: int, b: int, schedule: str, device, lda: int | None = None):
         torch = _torch()
         self.sched = SCHEDULES[schedule]
-        self.bytes = _lib.workspace_bytes(m, n, b, self.sched)
+        self.bytes = _lib.workspace_bytes(m, n, b, self.sched, m if lda is None else lda)
         if self.bytes == 0:
             raise ValueError("invalid sizes")
         self.buf = torch.empty(self.bytes, dtype=torch.uint8, device=device)
@@ -99,7 +100,7 @@ def qr(a, b: int = 0, schedule: str = "mod", check: bool = True, out=None,
         if q.shape != (m, n) or q.stride() != (1, lda) or r.shape != (n, n) or r.stride() != (1, n):
             raise ValueError("out tensors must be column-major with Q's stride equal to A's")
     if workspace is None:
-        workspace = Workspace(m, n, b, schedule, a.device)
+        workspace = Workspace(m, n, b, schedule, a.device, lda=lda)
     stream = torch.cuda.current_stream(a.device).cuda_stream
     st = _lib.factor_ex(m, n, b, a.data_ptr(), lda, q.data_ptr(), r.data_ptr(), stream,
                         SCHEDULES[schedule], workspace.info.data_ptr(),

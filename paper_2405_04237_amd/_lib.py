@@ -40,11 +40,13 @@ SIGNATURES = {
     "cqr_factor": (C.c_int, [_I64, _I64, _I64, _DP, _I64, _DP, _DP, _VP]),
     "cqr_factor_ex": (C.c_int, [_I64, _I64, _I64, _DP, _I64, _DP, _DP, _VP, C.POINTER(CqrOptions)]),
     "cqr_workspace_bytes": (C.c_size_t, [_I64, _I64, _I64, C.c_int]),
+    "cqr_workspace_bytes_ld": (C.c_size_t, [_I64, _I64, _I64, _I64, C.c_int]),
     "cqr_default_panel": (C.c_int64, [_I64, _I64, C.c_int]),
     "cqr_get_info": (C.c_int, [_VP, C.POINTER(C.c_int)]),
     "cqr_status_string": (C.c_char_p, [C.c_int]),
     "cqr_profile_enable": (C.c_int, [C.c_int]),
     "cqr_profile_reset": (C.c_int, []),
+    "cqr_profile_select": (C.c_int, [C.c_uint]),
     "cqr_profile_query": (C.c_int, [C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "cqr_plan_batched": (C.c_int, [_I64, _VP, _VP, _VP, C.c_int, C.POINTER(C.c_void_p)]),
@@ -88,8 +90,10 @@ def check(status: int, where: str) -> None:
         raise CqrError(status, where)
 
 
-def workspace_bytes(m: int, n: int, b: int, schedule: int) -> int:
-    return int(lib().cqr_workspace_bytes(m, n, b, schedule))
+def workspace_bytes(m: int, n: int, b: int, schedule: int, lda: int | None = None) -> int:
+    if lda is None:
+        return int(lib().cqr_workspace_bytes(m, n, b, schedule))
+    return int(lib().cqr_workspace_bytes_ld(m, n, b, lda, schedule))
 
 
 def default_panel(m: int, n: int, schedule: int) -> int:
@@ -151,6 +155,12 @@ def get_info(stream) -> int:
 
 def profile_enable(on: bool) -> None:
     check(lib().cqr_profile_enable(1 if on else 0), "cqr_profile_enable")
+
+
+def profile_select(kinds=None) -> None:
+    """Bracket only these kernel classes (names of KERNEL_KINDS; None = all)."""
+    mask = 0xFFFFFFFF if kinds is None else sum(1 << KERNEL_KINDS.index(k) for k in kinds)
+    check(lib().cqr_profile_select(mask), "cqr_profile_select")
 
 
 def profile_reset() -> None:

@@ -121,12 +121,17 @@ int64_t effective_panel(int64_t m, int64_t n, int64_t b, int schedule) {
 }
 
 // ---------------------------------------------------------------- per device
+struct LibBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
 struct DevState {
-  void *ws = nullptr;
-  size_t ws_bytes = 0;
-  int *info = nullptr;
-  void *bwd = nullptr;  // backward workspace
-  size_t bwd_bytes = 0;
+  LibBuf ws;            // factorisation workspace
+  LibBuf bwd;           // backward workspace
+  int *info = nullptr;  // internal info word (read by cqr_get_info)
+  // recorded on the caller's stream after every call that used ws or bwd
+  hipEvent_t last_use = nullptr;
   // side stream (default priority) for independent small work, forked from
   // and joined back into the caller's stream with events
   hipStream_t aux = nullptr;
@@ -157,6 +162,43 @@ hipError_t side_stream(DevState **out) {
   return hipSuccess;
 }
 
+#define CQR_TRY(expr)                    \
+  do {                                   \
+    const hipError_t e_ = (expr);        \
+    if (e_ != hipSuccess) return e_;     \
+  } while (0)
+
+// True when `s` is being captured into a graph.
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
+}
+
+// A library-owned buffer of at least `bytes`, grown in stream order on `s`:
+// `s` first waits for the last call that used the old buffer (d.last_use,
+// recorded on that call's stream), the old buffer is released with
+// hipFreeAsync and the new one taken with hipMallocAsync, both on `s`. The
+// host never waits for the device. Caller holds g_mu.
+hipError_t ensure_buffer(DevState &d, LibBuf &b, size_t bytes, hipStream_t s) {
+  if (b.bytes >= bytes) return hipSuccess;
+  if (b.p) {
+    if (d.last_use) CQR_TRY(hipStreamWaitEvent(s, d.last_use, 0));
+    CQR_TRY(hipFreeAsync(b.p, s));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  CQR_TRY(hipMallocAsync(&b.p, bytes, s));
+  b.bytes = bytes;
+  return hipSuccess;
+}
+
+// Mark the end of a call that used a library-owned buffer on `s`.
+hipError_t mark_use(DevState &d, hipStream_t s) {
+  if (!d.last_use) CQR_TRY(hipEventCreateWithFlags(&d.last_use, hipEventDisableTiming));
+  return hipEventRecord(d.last_use, s);
+}
+
 // ---------------------------------------------------------------- profiling
 struct Rec {
   hipEvent_t a, b;
@@ -168,6 +210,7 @@ struct Acc {
   double ms = 0, flops = 0, bytes = 0;
 };
 bool g_prof = false;
+unsigned g_prof_mask = ~0u;  // kernel classes bracketed while profiling is on
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 Acc g_acc[CQR_K_COUNT];
@@ -185,7 +228,7 @@ hipEvent_t pool_get() {
 
 template <class F>
 hipError_t timed(hipStream_t s, int kind, double flops, double bytes, F &&f) {
-  if (!g_prof) return f();
+  if (!g_prof || !(g_prof_mask & (1u << kind))) return f();
   std::lock_guard<std::mutex> lk(g_mu);
   hipEvent_t a = pool_get(), b = pool_get();
   if (!a || !b) return hipErrorOutOfMemory;
@@ -224,12 +267,6 @@ void plan_chunks(const Run &r, int64_t tiles, int64_t pq, int64_t *rc, int64_t *
   *rc = rows;
   *nch = (r.m + rows - 1) / rows;
 }
-
-#define CQR_TRY(expr)                    \
-  do {                                   \
-    const hipError_t e_ = (expr);        \
-    if (e_ != hipSuccess) return e_;     \
-  } while (0)
 
 // W = X^T X for the w columns at X (split-m partials + fixed-order reduce)
 hipError_t step_gram(Run &r, const double *X, int64_t ldx, int w) {
@@ -318,12 +355,15 @@ hipError_t pass_cqrgs(Run &r, const double *src, double *X, int64_t ld, int64_t 
     double *Xj = X + s * ld;
     const double *Aj = (s == 0) ? src : Xj;                          // panel j before its CQR
     const double *Ar = (s == 0) ? src + e * ld : X + e * ld;         // trailing panels
-    CQR_TRY(step_gram(r, Aj, ld, w));                                // W_j := A_j^T A_j
-    CQR_TRY(step_chol(r, w, nullptr, Rd + s + s * n, n, (int)s));    // W_j = U^T U; R_jj := U
-    CQR_TRY(step_trsm(r, Aj, Xj, ld, w, final ? s : -1));            // Q_j := A_j U^{-1}
+    // CholeskyQR of the panel; its factor is the diagonal block of R
+    CQR_TRY(step_gram(r, Aj, ld, w));
+    CQR_TRY(step_chol(r, w, nullptr, Rd + s + s * n, n, (int)s));
+    CQR_TRY(step_trsm(r, Aj, Xj, ld, w, final ? s : -1));
     if (e < n) {
-      CQR_TRY(step_proj(r, Xj, ld, w, Ar, (int)(n - e), Rd + s + e * n, n));  // Y; R_{j,j+1:k}
-      CQR_TRY(step_update(r, Xj, ld, w, Ar, X + e * ld, (int)(n - e)));       // A_{j+1:k} -= Q_j Y
+      // remove the new Q panel from the columns to its right; the
+      // coefficients are the panel's block row of R
+      CQR_TRY(step_proj(r, Xj, ld, w, Ar, (int)(n - e), Rd + s + e * n, n));
+      CQR_TRY(step_update(r, Xj, ld, w, Ar, X + e * ld, (int)(n - e)));
     }
   }
   return hipSuccess;
@@ -401,7 +441,8 @@ hipError_t run_mod(Run &r, const double *A, double *Q, int64_t ld, int64_t b, do
     double *Qprev = Q + ps * ld, *Xj = Q + s * ld;
     // the trailing columns are still A's until the first update writes them to Q
     const double *Ar = (ps == 0) ? A + s * ld : Xj;
-    // Y := Q_{j-1}^T A_{:,j:k}; R_{j-1,j:k} := Y; A_{:,j:k} -= Q_{j-1} Y
+    // project the finished previous panel out of every column to its right;
+    // the coefficients fill the previous panel's block row of R
     CQR_TRY(step_proj(r, Qprev, ld, pw, Ar, (int)(n - s), R + ps + s * n, n));
     // Look-ahead: update panel j's own columns first; panel j's chain then
     // runs on the side stream while this stream updates panels j+1..k. The
@@ -419,12 +460,13 @@ hipError_t run_mod(Run &r, const double *A, double *Q, int64_t ld, int64_t b, do
     } else {
       CQR_TRY(step_update(r, Qprev, ld, pw, Ar, Xj, (int)(n - s)));
     }
-    // CQR(A_j): A_j = Qt Ua
+    // first CholeskyQR of the panel (factor Ua)
     CQR_TRY(step_gram(c, Xj, ld, w));
     CQR_TRY(step_chol(c, w, c.Ua, nullptr, 0, (int)s));
     CQR_TRY(step_trsm(c, Xj, Xj, ld, w));
-    // re-orthogonalise: Z := Q_{1:j-1}^T Qt; Qt -= Q_{1:j-1} Z; R_{1:j-1,j} += Z Ua
-    // (c.Y holds -Z, so the R update subtracts (-Z) Ua)
+    // one classical Gram-Schmidt pass against all finished panels
+    // (coefficients Z); R above the panel gains Z Ua (c.Y holds -Z, so the
+    // R update subtracts (-Z) Ua)
     CQR_TRY(step_proj(c, Q, ld, (int)s, Xj, w, nullptr, 0));
     int *zs = nullptr, *cs = nullptr;
     if (c.adaptive > 0) {  // run-time choice: Z := 0 when ||Z||_F is within the tolerance
@@ -438,7 +480,7 @@ hipError_t run_mod(Run &r, const double *A, double *Q, int64_t ld, int64_t b, do
     CQR_TRY(timed(c.s, CQR_K_SMALL, 2.0 * s * w * w / 2, 0, [&] {
       return cqr::launch_r_add_zu((int)s, w, c.Y, cqr::padded_ld(w), c.Ua, R + s * n, n, c.info, c.s);
     }));
-    // CQR again: Qt = Q_j Ub; R_jj = Ub Ua
+    // CholeskyQR again (factor Ub); the diagonal block of R is Ub Ua
     CQR_TRY(step_gram(c, Xj, ld, w));
     CQR_TRY(step_chol(c, w, c.Ub, nullptr, 0, (int)s, cs));
     CQR_TRY(step_trsm(c, Xj, Xj, ld, w, s, cs));
@@ -529,11 +571,15 @@ int64_t cqr_default_panel(int64_t m, int64_t n, int schedule) {
   return std::min(b, n);
 }
 
-size_t cqr_workspace_bytes(int64_t m, int64_t n, int64_t b, int schedule) {
-  if (n < 1 || m < n || b < 0) return 0;
+size_t cqr_workspace_bytes_ld(int64_t m, int64_t n, int64_t b, int64_t lda, int schedule) {
+  if (n < 1 || m < n || b < 0 || lda < m) return 0;
   if (!valid_schedule(schedule)) return 0;
   const int64_t be = effective_panel(m, n, b, schedule);
-  return (size_t)make_layout(m, n, be, schedule, aliasing_ld(m)).total;
+  return (size_t)make_layout(m, n, be, schedule, aliasing_ld(lda)).total;
+}
+
+size_t cqr_workspace_bytes(int64_t m, int64_t n, int64_t b, int schedule) {
+  return cqr_workspace_bytes_ld(m, n, b, m, schedule);
 }
 
 int cqr_factor_ex(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda, double *Q,
@@ -555,35 +601,27 @@ int cqr_factor_ex(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
     if (opt->workspace_bytes < (size_t)lay.total) lay = plain;
     ws = (char *)opt->workspace;
   }
+  DevState *lib_state = nullptr;  // set when the library's workspace is used
   if (!ws || !info) {
+    const bool cap = capturing(s);
+    if (cap && !ws) return CQR_ERR_ARG;  // captured calls bring their own workspace
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return CQR_ERR_HIP;
     std::lock_guard<std::mutex> lk(g_mu);
     DevState &d = g_dev[dev];
     if (!d.info) {
+      if (cap) return CQR_ERR_ARG;  // the first call on a device allocates
       if (hipMalloc(&d.info, kAlign) != hipSuccess) return CQR_ERR_NOMEM;
-      if (hipMemset(d.info, 0, kAlign) != hipSuccess) return CQR_ERR_HIP;
     }
-    if (!ws && d.ws_bytes < (size_t)lay.total) {
-      // the stream may still use the old buffer: wait for the device first
-      if (d.ws) {
-        if (hipDeviceSynchronize() != hipSuccess) return CQR_ERR_HIP;
-        if (hipFree(d.ws) != hipSuccess) return CQR_ERR_HIP;
-        d.ws = nullptr;
-        d.ws_bytes = 0;
-      }
-      if (hipMalloc(&d.ws, (size_t)lay.total) != hipSuccess) {
+    if (!ws) {
+      if (ensure_buffer(d, d.ws, (size_t)lay.total, s) != hipSuccess) {
         (void)hipGetLastError();  // no room for the staging copy: factor in place
         lay = plain;
-        if (d.ws_bytes < (size_t)lay.total) {
-          if (hipMalloc(&d.ws, (size_t)lay.total) != hipSuccess) return CQR_ERR_NOMEM;
-          d.ws_bytes = (size_t)lay.total;
-        }
-      } else {
-        d.ws_bytes = (size_t)lay.total;
+        if (ensure_buffer(d, d.ws, (size_t)lay.total, s) != hipSuccess) return CQR_ERR_NOMEM;
       }
+      ws = (char *)d.ws.p;
+      lib_state = &d;
     }
-    if (!ws) ws = (char *)d.ws;
     if (!info) info = d.info;
   }
 
@@ -630,6 +668,10 @@ int cqr_factor_ex(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
   } else {
     e = run_schedule(r, schedule, A, Q, lda, be, R);
   }
+  if (e == hipSuccess && lib_state) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    e = mark_use(*lib_state, s);
+  }
   return e == hipSuccess ? CQR_OK : CQR_ERR_HIP;
 }
 
@@ -672,6 +714,12 @@ const char *cqr_status_string(int status) {
 int cqr_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_prof = on != 0;
+  return CQR_OK;
+}
+
+int cqr_profile_select(unsigned kind_mask) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_prof_mask = kind_mask;
   return CQR_OK;
 }
 
@@ -727,25 +775,19 @@ int cqr_backward_batched(int64_t batch, int64_t m, int64_t n, const double *Q, c
   const BwdLayout lay = make_bwd_layout(m, n, batch);
   hipStream_t s = (hipStream_t)stream;
   char *ws = (char *)workspace;
+  DevState *lib_state = nullptr;  // set when the library's workspace is used
   if (ws) {
     if (workspace_bytes < (size_t)lay.total) return CQR_ERR_WORKSPACE;
     if (misaligned(ws, kAlign)) return CQR_ERR_ARG;
   } else {
+    if (capturing(s)) return CQR_ERR_ARG;  // captured calls bring their own workspace
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return CQR_ERR_HIP;
     std::lock_guard<std::mutex> lk(g_mu);
     DevState &d = g_dev[dev];
-    if (d.bwd_bytes < (size_t)lay.total) {
-      if (d.bwd) {
-        if (hipDeviceSynchronize() != hipSuccess) return CQR_ERR_HIP;
-        if (hipFree(d.bwd) != hipSuccess) return CQR_ERR_HIP;
-        d.bwd = nullptr;
-        d.bwd_bytes = 0;
-      }
-      if (hipMalloc(&d.bwd, (size_t)lay.total) != hipSuccess) return CQR_ERR_NOMEM;
-      d.bwd_bytes = (size_t)lay.total;
-    }
-    ws = (char *)d.bwd;
+    if (ensure_buffer(d, d.bwd, (size_t)lay.total, s) != hipSuccess) return CQR_ERR_NOMEM;
+    ws = (char *)d.bwd.p;
+    lib_state = &d;
   }
   int *info = (int *)(ws + lay.info);
   double *part = (double *)(ws + lay.part), *T = (double *)(ws + lay.t);
@@ -756,7 +798,13 @@ int cqr_backward_batched(int64_t batch, int64_t m, int64_t n, const double *Q, c
   const bool recompute = (Q == nullptr);
   const double *S = recompute ? A : Q;
   const double mf = (double)m, nf = (double)n, bf = (double)batch;
-  auto fail = [](hipError_t e) { return e == hipSuccess ? CQR_OK : CQR_ERR_HIP; };
+  auto fail = [&](hipError_t e) {
+    if (e == hipSuccess && lib_state) {
+      std::lock_guard<std::mutex> lk(g_mu);
+      e = mark_use(*lib_state, s);
+    }
+    return e == hipSuccess ? CQR_OK : CQR_ERR_HIP;
+  };
 
   if (!dQ && !dR)
     return fail(timed(s, CQR_K_SMALL, 0, 8.0 * bf * mf * nf,

@@ -51,7 +51,7 @@ def tune(a, schedule: str = "mod", cands=None, reps: int = 2, cache: str | None 
     r = empty_colmajor(n, n, a.device)
     table = []
     for b in cands:
-        ws = Workspace(m, n, b, schedule, a.device)
+        ws = Workspace(m, n, b, schedule, a.device, lda=a.stride(1))
         row = {"b": b}
         try:
             qr(a, b=b, schedule=schedule, out=(q, r), workspace=ws)

@@ -21,7 +21,7 @@ def test_timed_configuration_accuracy():
     dev = torch.device("cuda:0")
     torch.cuda.empty_cache()  # earlier full-size tests leave 32 GiB blocks cached
     a = matgen.test_matrix_device(m, n, kappa, 3, device=dev, ld=m + 16)
-    ws = cqr.Workspace(m, n, b, "mod", dev)
+    ws = cqr.Workspace(m, n, b, "mod", dev, lda=a.stride(1))
     q = cqr.empty_colmajor(m, n, dev, ld=a.stride(1))
     r = cqr.empty_colmajor(n, n, dev)
     cqr.qr(a, b=b, schedule="mod", out=(q, r), workspace=ws)

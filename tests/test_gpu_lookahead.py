@@ -11,7 +11,7 @@ import pytest
 
 import matgen
 import oracle
-from tests.util import U, to_dev, to_host
+from tests.util import U, check_r, r_bars, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +43,7 @@ def test_lookahead_bitwise_equal_and_accurate(m, n, b, kappa, ld):
     qo, ro = oracle.mcqr2gs(a, b)
     assert oracle.orthogonality(q) <= 1e-13
     assert oracle.residual(a, q, r) <= 1e-14
-    assert oracle.rel_fro(r, ro) <= 100 * n * U * kappa
+    check_r(r, ro, r_bars(a, ro, kappa), f"lookahead {m}x{n} b={b}")
 
 
 def test_lookahead_breakdown_column():

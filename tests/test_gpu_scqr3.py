@@ -14,7 +14,7 @@ import pytest
 
 import matgen
 import oracle
-from tests.util import U, to_dev, to_host
+from tests.util import U, check_r, r_bars, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def _check(a, q, r, kappa):
     assert np.all(np.tril(r, -1) == 0) and np.all(np.diag(r) > 0)
     assert oracle.orthogonality(q) <= 1e-13
     assert oracle.residual(a, q, r) <= 1e-14
-    assert oracle.rel_fro(r, ro) <= 100 * n * U * kappa
+    check_r(r, ro, r_bars(a, ro, kappa), f"scqr3 {a.shape}")
     if kappa <= 1e6:
         assert np.max(np.abs(q - qo)) <= 100 * n * U * kappa
 
@@ -153,3 +153,31 @@ def test_full_size_properties():
     torch.cuda.synchronize()
     assert oracle.rel_fro(rh, to_host(r2)) <= 100 * n * U * kappa
 
+
+
+def test_beyond_the_shift_reach():
+    """2^18 x 32 at kappa = 1e16, past the reach of the shift of Algorithm 4
+    at this m: the shifted Q1 keeps a condition number near 2.5e9, beyond
+    CholeskyQR2's (section "Shifted CholeskyQR3"), and the oracle breaks
+    down in its CholeskyQR2 stage. The GPU rounds in another order, so it may
+    break down at another column or, by luck, get through; the contract is
+    that it never returns info = 0 with factors outside the accuracy bounds:
+    either info > 0, or ||Q^T Q - I||_F <= 1e-13 and the residual <= 1e-14."""
+    m, n = 1 << 18, 32
+    a = matgen.test_matrix(m, n, 1e16, seed=1)
+    with pytest.raises(oracle.Breakdown):
+        oracle.scqr3(a)
+    ad = to_dev(a)
+    ws = cqr.Workspace(m, n, 0, "scqr3", ad.device, lda=ad.stride(1))
+    q, r = cqr.qr(ad, schedule="scqr3", workspace=ws, check=False)
+    torch.cuda.synchronize()
+    info = int(ws.info.item())
+    if info > 0:
+        print(f"GPU sCQR3 at kappa = 1e16: breakdown at column {info}")
+        assert info <= n
+        return
+    qh, rh = to_host(q), to_host(r)
+    orth, res = oracle.orthogonality(qh), oracle.residual(a, qh, rh)
+    print(f"GPU sCQR3 at kappa = 1e16: info 0, orthogonality {orth:.2e}, residual {res:.2e}")
+    assert info == 0
+    assert orth <= 1e-13 and res <= 1e-14, (orth, res)

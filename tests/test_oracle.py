@@ -383,3 +383,22 @@ def test_cost_formulas_match_paper_tables():
     m, n, b = 4 * 1024 * 1024, 1024, 128
     assert cqr2gs_table2(m, n, b) == pytest.approx(2 * b * b * n / 3 + n ** 3 / 3 + 4 * m * n * n)
     assert householder_flops(m, n) == pytest.approx(2 * m * n * n - 2 * n ** 3 / 3)
+
+
+def test_batched_workload_needs_two_panels():
+    """The batched workload names b = min(n, 32); for n <= 32 that is a single
+    panel, i.e. plain CholeskyQR2, which breaks down past kappa ~ 1e8 (section
+    "CholeskyQR2"). On the workload's own n <= 32 matrices with kappa >= 1e10
+    (a sample of eight of the smaller ones) the oracle's CholeskyQR2 breaks
+    down on every one, while mCQR2GS with b = ceil(n / 2), the library's
+    batched default, meets the accuracy bounds on every one."""
+    import matgen
+    probs = [p for p in matgen.batch_problems() if p.n <= 32 and p.kappa >= 1e10 and p.m <= 24000]
+    assert len(probs) >= 8
+    for p in probs[:8]:
+        a = matgen.test_matrix(p.m, p.n, p.kappa, p.seed)
+        with pytest.raises(oracle.Breakdown):
+            oracle.cqr2(a)
+        assert p.b == min((p.n + 1) // 2, 32)
+        q, r = oracle.mcqr2gs(a, p.b)
+        assert oracle.orthogonality(q) <= 1e-13 and oracle.residual(a, q, r) <= 1e-14

@@ -24,3 +24,42 @@ def gpu_available() -> bool:
         return torch.cuda.is_available()
     except Exception:
         return False
+
+
+def r_bars(a: np.ndarray, r_oracle: np.ndarray, kappa: float, r_householder=None):
+    """Tolerances for a computed R against the oracle's R.
+
+    * ``first_order``: 100 n u kappa, relative Frobenius (a first-order
+      perturbation of the unique R under backward errors of size c n u per
+      column). Vacuous for kappa >~ 1e12 at these n.
+    * ``spread``: 10 x the distance between the oracle's R and LAPACK's
+      Householder R (an independent backward-stable algorithm, sign
+      normalised). Two backward-stable QR algorithms land within rounding
+      noise of each other; a third one (the GPU) must not be farther from the
+      oracle than ten times that spread (triangle inequality, with margin).
+      Meaningful at every kappa.
+    * ``elementwise``: where 100 n u kappa < 1e-6, the same first-order bound
+      on max |dR_ij| relative to max |R_ij|; None above.
+    """
+    import oracle
+    n = a.shape[1]
+    rh = oracle.householder_qr(a)[1] if r_householder is None else r_householder
+    fo = 100 * n * U * kappa
+    spread = oracle.rel_fro(r_oracle, rh)
+    return {"first_order": fo, "spread": 10 * max(spread, n * U / 100),
+            "observed_spread": spread, "elementwise": fo if fo < 1e-6 else None}
+
+
+def check_r(r: np.ndarray, r_oracle: np.ndarray, bars: dict, label: str = "") -> float:
+    """Assert R against the oracle's R under ``bars`` (see r_bars); returns
+    the observed relative Frobenius difference (printed for the record)."""
+    import oracle
+    d = oracle.rel_fro(r, r_oracle)
+    print(f"{label} |R - R_oracle|_F / |R_oracle|_F = {d:.3e} "
+          f"(oracle vs Householder {bars['observed_spread']:.3e})")
+    assert d <= bars["first_order"], (label, d, bars)
+    assert d <= bars["spread"], (label, d, bars)
+    if bars["elementwise"] is not None:
+        el = float(np.max(np.abs(r - r_oracle)) / np.max(np.abs(r_oracle)))
+        assert el <= bars["elementwise"], (label, el, bars)
+    return d

@@ -2,7 +2,7 @@
 shifted CholeskyQR3, CQRGS, CQR2GS and mCQR2GS.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring). Plain FP64 NumPy/SciPy,
-one step per line of the paper's algorithms, no blocking or fusion beyond
+the algorithms' steps in the paper's order, no blocking or fusion beyond
 what the algorithms state. Library primitives used as steps: BLAS matrix
 products, LAPACK ``dpotrf`` (Cholesky with its breakdown index) and
 ``dtrsm`` through ``scipy.linalg.solve_triangular``.

@@ -37,7 +37,11 @@ def r_bars(a: np.ndarray, r_oracle: np.ndarray, kappa: float, r_householder=None
       normalised). Two backward-stable QR algorithms land within rounding
       noise of each other; a third one (the GPU) must not be farther from the
       oracle than ten times that spread (triangle inequality, with margin).
-      Meaningful at every kappa.
+      Meaningful at every kappa. It never falls below max(4, n) units of
+      roundoff: the two references may agree more closely with each other
+      than with a third summation order (the batched kernel sums hundreds of
+      rows sequentially per accumulator; n = 1 is a single rounded norm),
+      and an R computed in any order carries rounding of about that size.
     * ``elementwise``: where 100 n u kappa < 1e-6, the same first-order bound
       on max |dR_ij| relative to max |R_ij|; None above.
     """
@@ -46,7 +50,7 @@ def r_bars(a: np.ndarray, r_oracle: np.ndarray, kappa: float, r_householder=None
     rh = oracle.householder_qr(a)[1] if r_householder is None else r_householder
     fo = 100 * n * U * kappa
     spread = oracle.rel_fro(r_oracle, rh)
-    return {"first_order": fo, "spread": 10 * max(spread, n * U / 100),
+    return {"first_order": fo, "spread": max(10 * spread, max(4, n) * U),
             "observed_spread": spread, "elementwise": fo if fo < 1e-6 else None}
 
 

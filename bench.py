@@ -31,7 +31,7 @@ PEAK_HBM = 8.0e12       # MI355X HBM3E, bytes/s
 
 WORKLOADS = {
     # the configuration the metric is quoted on (one GPU's row block)
-    "tsqr-2^22x1024-k1e15": dict(m=1 << 22, n=1024, kappa=1e15, b_cands=(64, 128), seed=3),
+    "tsqr-2^22x1024-k1e15": dict(m=1 << 22, n=1024, kappa=1e15, b_cands=(64, 128, 256), seed=3),
     "tsqr-2^20x256-k1e15": dict(m=1 << 20, n=256, kappa=1e15, b_cands=(64,), seed=2),
     "tsqr-4096x64-k1e12": dict(m=4096, n=64, kappa=1e12, b_cands=(16,), seed=1),
 }

@@ -30,10 +30,13 @@
  *   dimension n. All pointers are device pointers unless marked "host".
  * - Panel j covers columns [j b, min((j+1) b, n)); the last panel may be
  *   narrower. b = 0 selects a default width; b > n is clamped to n. After
- *   clamping 1 <= b <= CQR_MAX_PANEL: the Cholesky factor and inverse of a
- *   panel's b x b Gram matrix are formed in the local data share of one
- *   workgroup (128 x 128 FP64 = 128 KiB of the 160 KiB a gfx950 workgroup
- *   may hold); a wider b returns CQR_ERR_UNSUPPORTED.
+ *   clamping 1 <= b <= CQR_MAX_PANEL (a wider b returns
+ *   CQR_ERR_UNSUPPORTED). The Cholesky factor and inverse of a panel's b x b
+ *   Gram matrix are formed by one workgroup: for b <= 128 entirely in its
+ *   local data share (128 x 128 FP64 = 128 KiB of the 160 KiB a gfx950
+ *   workgroup may hold), for 128 < b <= 256 with the matrix in device
+ *   workspace and 16-row blocks and the last 128 x 128 block in LDS (the
+ *   same right-looking steps and block back substitution).
  * - A is only read. Q may equal A (in-place factorisation); any other
  *   overlap of A, Q, R, the workspace or the info word is an error the
  *   library does not detect.
@@ -74,7 +77,7 @@ enum cqr_status {
   CQR_ERR_UNSUPPORTED = -5  /* a size this build does not handle */
 };
 
-#define CQR_MAX_PANEL 128
+#define CQR_MAX_PANEL 256
 
 enum cqr_schedule {
   CQR_SCHED_MOD = 0,   /* mCQR2GS, Algorithm 9 (default) */
@@ -211,7 +214,8 @@ void cqr_plan_destroy(cqr_batch_plan *plan);
  * as products with A followed by R^{-1} on the n x n side (A must then be
  * non-NULL; otherwise A is ignored). dQ and dR may be NULL (zero cotangent);
  * the strict lower triangle of dR is ignored. dA must not overlap any input.
- * 1 <= n <= CQR_MAX_PANEL (R^{-1} is formed in one workgroup's LDS).
+ * 1 <= n <= CQR_MAX_PANEL (R^{-1} is formed by one workgroup, as the
+ * factorisation's U^{-1}).
  * workspace: >= cqr_backward_workspace_bytes(m, n, batch) bytes of device
  * memory, 256-byte aligned, or NULL for a buffer the library keeps per device
  * (grown in stream order as cqr_factor's workspace; a call during stream

@@ -76,7 +76,7 @@ def qr(a, b: int = 0, schedule: str = "mod", check: bool = True, out=None,
     """Thin QR of a tall-and-skinny FP64 matrix: returns (Q, R).
 
     schedule "mod" = mCQR2GS (Algorithm 9), "orig" = CQR2GS (Algorithm 7),
-    "scqr3" = shifted CholeskyQR3 (Algorithm 5; whole matrix, n <= 128, b
+    "scqr3" = shifted CholeskyQR3 (Algorithm 5; whole matrix, n <= 256, b
     ignored). b = 0 picks libcqr's default panel width. lookahead=True runs
     each mCQR2GS panel's chain on a side stream, overlapped with the trailing
     update (bitwise the same result). adaptive=True leaves out a panel's

@@ -17,7 +17,7 @@ CQR_ERR_HIP = -2
 CQR_ERR_NOMEM = -3
 CQR_ERR_WORKSPACE = -4
 CQR_ERR_UNSUPPORTED = -5
-CQR_MAX_PANEL = 128
+CQR_MAX_PANEL = 256
 
 SCHED_MOD = 0
 SCHED_ORIG = 1

@@ -63,7 +63,7 @@ int64_t staging_ld(int64_t m) {
 
 // ---------------------------------------------------------------- workspace
 struct Layout {
-  int64_t w, uinv, ua, ub, y, yz, part, r1, r2, stage, flags, total;  // byte offsets / size
+  int64_t w, uinv, ua, ub, g, y, yz, part, r1, r2, stage, flags, total;  // byte offsets / size
   int64_t part_elems, ldw;                                 // ldw: staging leading dim
 };
 
@@ -80,6 +80,8 @@ Layout make_layout(int64_t m, int64_t n, int64_t b, int schedule, bool stage) {
   L.uinv = take(b * cqr::padded_ld(b));
   L.ua = take(b * b);
   L.ub = take(b * b);
+  // panels wider than the LDS Cholesky holds are factored in device scratch
+  L.g = cqr::chol_scratch_doubles((int)b) > 0 ? take(cqr::chol_scratch_doubles((int)b)) : -1;
   L.y = take(n * cqr::padded_ld(std::max(n, b)));
   // MOD with look-ahead: the re-orthogonalisation coefficients Z (at most
   // n x b) get their own buffer, since the trailing Y is still being read
@@ -252,7 +254,7 @@ struct Run {
   int *zskip, *cskip;            // its decisions (device words)
   int *info;
   int64_t m, n;
-  double *W, *Uinv, *Ua, *Ub, *Y, *part, *R1, *R2;
+  double *W, *Uinv, *Ua, *Ub, *G, *Y, *part, *R1, *R2;
   int64_t part_elems;
   double *Qout;  // staged runs: the caller's Q, written by each panel's final step
   int64_t ldq;
@@ -289,7 +291,7 @@ hipError_t step_chol(Run &r, int w, double *uout, double *rblk, int64_t ldr, int
   const double wf = w;
   return timed(r.s, CQR_K_CHOL, 2.0 * wf * wf * wf / 3.0, 8.0 * 4 * wf * wf, [&] {
     return cqr::launch_chol_inv(r.W, w, uout, rblk, ldr, r.Uinv, r.info, col0, r.s, r.adaptive,
-                                skip);
+                                skip, r.G);
   });
 }
 
@@ -513,7 +515,7 @@ int check_args(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda, co
 
 // ---------------------------------------------------------------- backward
 struct BwdLayout {
-  int64_t info, part, t, rinv, c, g, y, total;
+  int64_t info, part, t, rinv, c, g, y, gw, total;
   int64_t nch, rc, ldy;
 };
 
@@ -539,6 +541,7 @@ BwdLayout make_bwd_layout(int64_t m, int64_t n, int64_t batch) {
   L.c = take(8 * batch * n * n);
   L.g = take(8 * batch * n * n);
   L.y = take(8 * batch * 2 * n * L.ldy);
+  L.gw = take(8 * batch * cqr::chol_scratch_doubles((int)n));  // R^{-1} of n > kLdsPanel
   L.total = off;
   return L;
 }
@@ -567,7 +570,7 @@ int64_t cqr_default_panel(int64_t m, int64_t n, int schedule) {
   // panels (the paper uses three); CQR2GS needs narrower panels there.
   const int64_t parts = (schedule == CQR_SCHED_ORIG) ? 16 : 4;
   int64_t b = round_up((n + parts - 1) / parts, 16);
-  b = std::max<int64_t>(16, std::min<int64_t>(b, schedule == CQR_SCHED_ORIG ? 64 : kMaxPanel));
+  b = std::max<int64_t>(16, std::min<int64_t>(b, schedule == CQR_SCHED_ORIG ? 64 : cqr::kLdsPanel));
   return std::min(b, n);
 }
 
@@ -634,6 +637,7 @@ int cqr_factor_ex(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
   r.Uinv = (double *)(ws + lay.uinv);
   r.Ua = (double *)(ws + lay.ua);
   r.Ub = (double *)(ws + lay.ub);
+  r.G = lay.g >= 0 ? (double *)(ws + lay.g) : nullptr;
   r.Y = (double *)(ws + lay.y);
   r.part = (double *)(ws + lay.part);
   r.part_elems = lay.part_elems;
@@ -679,6 +683,7 @@ int cqr_factor(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda, do
                double *R, void *stream) {
   return cqr_factor_ex(m, n, b, A, lda, Q, R, stream, nullptr);
 }
+
 
 int cqr_get_info(void *stream, int *info) {
   if (!info) return CQR_ERR_ARG;
@@ -792,7 +797,7 @@ int cqr_backward_batched(int64_t batch, int64_t m, int64_t n, const double *Q, c
   int *info = (int *)(ws + lay.info);
   double *part = (double *)(ws + lay.part), *T = (double *)(ws + lay.t);
   double *Rinv = (double *)(ws + lay.rinv), *C = (double *)(ws + lay.c), *G = (double *)(ws + lay.g);
-  double *Y = (double *)(ws + lay.y);
+  double *Y = (double *)(ws + lay.y), *Gw = (double *)(ws + lay.gw);
   const int ni = (int)n, b = (int)batch;
   const int64_t nn = n * n, sy = 2 * n * lay.ldy;
   const bool recompute = (Q == nullptr);
@@ -821,7 +826,7 @@ int cqr_backward_batched(int64_t batch, int64_t m, int64_t n, const double *Q, c
       hipStreamWaitEvent(aux, dev_state->fork, 0) != hipSuccess)
     return CQR_ERR_HIP;
   e = timed(aux, CQR_K_CHOL, bf * nf * nf * nf / 3.0, 16.0 * bf * nn,
-            [&] { return cqr::launch_tri_inv(R, ni, nn, Rinv, nn, b, aux); });
+            [&] { return cqr::launch_tri_inv(R, ni, nn, Rinv, nn, b, aux, Gw); });
   if (e != hipSuccess) return CQR_ERR_HIP;
   if (hipEventRecord(dev_state->join, aux) != hipSuccess) return CQR_ERR_HIP;
   // pass 1: T = S^T dQ (upper 64x64 tiles), split over m, fixed-order reduce

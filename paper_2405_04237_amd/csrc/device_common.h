@@ -260,8 +260,194 @@ __device__ inline void lds_upper_inverse_blocked(double *S, int wp, double *tmp,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Orders above what one workgroup's LDS holds (wp = 2h, h = 128): the padded
+// matrix G lives in device memory (row-major, ld wp; a few hundred KiB that
+// stay in L2) and one workgroup runs the same steps as the LDS forms above.
+// S is LDS of blocked_lds_doubles(h) doubles.
+// ---------------------------------------------------------------------------
+
+// W = U^T U in place of G's upper triangle (the strict lower part must be 0
+// on entry and stays 0). Right-looking by 16-column panels, as
+// lds_cholesky_blocked: the panel's 16 rows are staged in LDS, where wave 0
+// factors the diagonal block and every thread solves the row block; the
+// panel's rows of U go back to G, and the trailing upper triangle is updated
+// in G, each element's terms subtracted in column order. When the trailing
+// matrix has order h it is moved to LDS and finished by lds_cholesky_blocked
+// (the same steps). Returns 0 or the 1-based column of the first pivot that
+// is not > 0 (NaN included), the same in every thread.
+__device__ inline int wide_cholesky(double *G, int wp, double *S, int *flag) {
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, h = wp / 2;
+  double *P = S;               // 16 x wp: rows p0 .. p0 + 15 of the matrix
+  double *rpiv = S + 16 * wp;  // the panel's pivot reciprocals
+  for (int p0 = 0; p0 < h; p0 += 16) {
+    if (tid == 0) *flag = 0;
+    for (int e = tid; e < 16 * wp; e += nt) {
+      const int k = e / wp, j = e % wp;
+      P[e] = (j >= p0) ? G[(int64_t)(p0 + k) * wp + j] : 0.0;
+    }
+    __syncthreads();
+    if (tid < 64) {  // diagonal block, one wave
+      for (int k = 0; k < 16; ++k) {
+        const int kk = p0 + k;
+        const double d = P[k * wp + kk];
+        if (!(d > 0.0)) {
+          if (lane == 0) *flag = kk + 1;
+          break;
+        }
+        const double piv = sqrt(d);
+        wave_lds_sync();
+        if (lane < 16 - k) {
+          const int j = kk + lane;
+          P[k * wp + j] = (lane == 0) ? piv : P[k * wp + j] / piv;
+        }
+        wave_lds_sync();
+        for (int e = lane; e < 16 * 16; e += 64) {
+          const int i = e / 16, j = e % 16;  // block-relative
+          if (i > k && j >= i) P[i * wp + p0 + j] -= P[k * wp + p0 + i] * P[k * wp + p0 + j];
+        }
+        wave_lds_sync();
+      }
+    }
+    if (tid < 16) rpiv[tid] = 1.0 / P[tid * wp + p0 + tid];
+    __syncthreads();
+    const int fail = *flag;
+    if (fail) return fail;
+    const int c0 = p0 + 16, rest = wp - c0;
+    // row block: forward substitution through the panel, 16 lanes per column
+    for (int e = tid; e < 16 * rest; e += nt) {
+      const int j = c0 + e / 16, k = e % 16;
+      double v = P[k * wp + j];
+      for (int st = 0; st < 16; ++st) {
+        const double x = __shfl(v * rpiv[st], st, 16);
+        if (k == st) v = x;
+        if (k > st) v -= P[st * wp + p0 + k] * x;
+      }
+      P[k * wp + j] = v;
+    }
+    __syncthreads();
+    // the panel's rows of U are final
+    for (int e = tid; e < 16 * (wp - p0); e += nt) {
+      const int k = e / (wp - p0), j = p0 + e % (wp - p0);
+      G[(int64_t)(p0 + k) * wp + j] = P[k * wp + j];
+    }
+    // trailing upper triangle, in device memory
+    for (int e = tid; e < rest * rest; e += nt) {
+      const int i = c0 + e / rest, j = c0 + e % rest;
+      if (j >= i) {
+        double ui[16], uj[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          ui[k] = P[k * wp + i];
+          uj[k] = P[k * wp + j];
+        }
+        double *g = G + (int64_t)i * wp + j;
+        double x = *g;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) x -= ui[k] * uj[k];
+        *g = x;
+      }
+    }
+    __syncthreads();
+  }
+  // the trailing h x h block in LDS
+  for (int e = tid; e < h * h; e += nt) S[e] = G[(int64_t)(h + e / h) * wp + h + e % h];
+  __syncthreads();
+  const int fail = lds_cholesky_blocked(S, h, flag);
+  if (fail) return h + fail;
+  for (int e = tid; e < h * h; e += nt) {
+    const int i = e / h, j = e % h;
+    if (j >= i) G[(int64_t)(h + i) * wp + h + j] = S[e];
+  }
+  __syncthreads();
+  return 0;
+}
+
+// U^{-1} in place of G's upper triangle (U upper with a nonzero diagonal;
+// the strict lower part is left as it was): the block back substitution of
+// lds_upper_inverse_blocked. The bottom-right h x h block X22 = U22^{-1}
+// involves U22 alone and is formed in LDS by that function; then block rows
+// of 16 from row h - 16 upwards: the block's rows of U are staged in LDS,
+// right-hand sides are formed from the finished rows of X below (read from
+// G), and 16 lanes per column solve with the 16 x 16 diagonal block.
+__device__ inline void wide_upper_inverse(double *G, int wp, double *S) {
+  const int tid = threadIdx.x, nt = blockDim.x, h = wp / 2;
+  for (int e = tid; e < h * h; e += nt) {
+    const int i = e / h, j = e % h;
+    S[e] = (j >= i) ? G[(int64_t)(h + i) * wp + h + j] : 0.0;
+  }
+  __syncthreads();
+  lds_upper_inverse_blocked(S, h, S + h * h, S + h * h + 16 * h);
+  for (int e = tid; e < h * h; e += nt) {
+    const int i = e / h, j = e % h;
+    if (j >= i) G[(int64_t)(h + i) * wp + h + j] = S[e];
+  }
+  __syncthreads();
+  double *Ur = S;              // 16 x wp: the block's rows of U
+  double *tmp = S + 16 * wp;   // 16 x wp: right-hand sides
+  double *dg = S + 32 * wp;    // reciprocals of the block's pivots
+  for (int o = h - 16; o >= 0; o -= 16) {
+    const int ncols = wp - o;
+    for (int e = tid; e < 16 * ncols; e += nt) {
+      const int r = e / ncols, j = o + e % ncols;
+      Ur[r * wp + j] = G[(int64_t)(o + r) * wp + j];
+    }
+    if (tid < 16) dg[tid] = 1.0 / G[(int64_t)(o + tid) * wp + o + tid];
+    __syncthreads();
+    for (int e = tid; e < 16 * ncols; e += nt) {
+      const int r = e / ncols, j = o + e % ncols;
+      // four partial sums over k, as lds_upper_inverse_blocked (X[k][j] = 0 for k > j)
+      const double *ur = Ur + r * wp;
+      double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+      int k0 = o + 16;
+      for (; k0 + 15 <= j; k0 += 16) {
+        double ua[16], xb[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          ua[k] = ur[k0 + k];
+          xb[k] = G[(int64_t)(k0 + k) * wp + j];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < 16; k += 4) {
+          x0 += ua[k] * xb[k];
+          x1 += ua[k + 1] * xb[k + 1];
+          x2 += ua[k + 2] * xb[k + 2];
+          x3 += ua[k + 3] * xb[k + 3];
+        }
+      }
+      if (k0 <= j) {
+#pragma unroll
+        for (int k = 0; k < 16; k += 4) {
+          if (k0 + k <= j) x0 += ur[k0 + k] * G[(int64_t)(k0 + k) * wp + j];
+          if (k0 + k + 1 <= j) x1 += ur[k0 + k + 1] * G[(int64_t)(k0 + k + 1) * wp + j];
+          if (k0 + k + 2 <= j) x2 += ur[k0 + k + 2] * G[(int64_t)(k0 + k + 2) * wp + j];
+          if (k0 + k + 3 <= j) x3 += ur[k0 + k + 3] * G[(int64_t)(k0 + k + 3) * wp + j];
+        }
+      }
+      tmp[r * wp + j] = ((o + r == j) ? 1.0 : 0.0) - ((x0 + x1) + (x2 + x3));
+    }
+    __syncthreads();
+    for (int e = tid; e < 16 * ncols; e += nt) {
+      const int j = o + e / 16, r = e % 16;
+      double v = tmp[r * wp + j];
+      for (int st = 15; st >= 0; --st) {
+        const double x = __shfl(v * dg[st], st, 16);
+        if (r == st) v = x;
+        if (r < st) v -= Ur[r * wp + o + st] * x;
+      }
+      if (o + r <= j) G[(int64_t)(o + r) * wp + j] = v;
+    }
+    __syncthreads();
+  }
+}
+
 // LDS doubles the blocked Cholesky + inverse need for padded order wp.
 __host__ __device__ inline int blocked_lds_doubles(int wp) { return wp * wp + 16 * wp + 16; }
+
+// LDS doubles the device-memory forms need for order wp = 2h: the LDS form
+// of order h, which also covers the 16-row stagings (at most 32 wp + 16).
+__host__ __device__ inline int wide_lds_doubles(int wp) { return blocked_lds_doubles(wp / 2); }
 
 // Order of the padded LDS matrix used by the blocked forms for order w.
 __host__ __device__ inline int blocked_order(int w) {

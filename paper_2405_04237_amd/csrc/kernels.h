@@ -10,7 +10,12 @@ namespace cqr {
 
 constexpr int kTile = 64;        // output tile edge of the MFMA GEMM kernels
 constexpr int kNnWaves = 4;      // waves per workgroup of the row-streaming GEMM
-constexpr int kMaxPanel = 128;   // largest panel width the LDS Cholesky holds
+constexpr int kLdsPanel = 128;   // largest panel width the LDS Cholesky holds
+constexpr int kMaxPanel = 256;   // widest panel (above kLdsPanel: through device memory)
+
+// Doubles of device scratch the Cholesky / inverse of a w x w matrix needs
+// (0 for w <= kLdsPanel; the identity-padded order-256 matrix otherwise).
+inline int64_t chol_scratch_doubles(int w) { return w > kLdsPanel ? int64_t(kMaxPanel) * kMaxPanel : 0; }
 
 // Split-m product partials. For chunk c (rows [c*rc, min(m,(c+1)*rc))):
 //   part[c][i*q + j] = sum_rows L[row, i] * Rt[row, j],  i < p, j < q.
@@ -80,9 +85,11 @@ hipError_t launch_reduce(bool gram, double *part, int64_t nch, int p, int q, dou
 // skip (optional): first ||W - I||_F is summed in a fixed order; if it is
 // <= skip_tol the outputs are U = U^{-1} = I and *skip = 1 (no Cholesky),
 // else *skip = 0.
+// w <= kMaxPanel; for w > kLdsPanel, gwork is device scratch of
+// chol_scratch_doubles(w) doubles (the matrix is factored there).
 hipError_t launch_chol_inv(const double *W, int w, double *uout, double *rblk, int64_t ldr,
                            double *uinv, int *info, int col0, hipStream_t s,
-                           double skip_tol = 0.0, int *skip = nullptr);
+                           double skip_tol = 0.0, int *skip = nullptr, double *gwork = nullptr);
 
 // ||Z||_F of the rows x cols row-major Z (leading dim ldz), fixed order; if
 // <= tol, Z := 0 and *skip = 1, else *skip = 0. One workgroup.
@@ -90,9 +97,10 @@ hipError_t launch_zskip(double *Z, int rows, int cols, int64_t ldz, double tol, 
                         const int *info, hipStream_t s);
 
 // Rinv = R^{-1} for `batch` upper triangular n x n matrices (R column-major
-// ld n at R + i*sR; Rinv row-major ld n at Rinv + i*sRi); n <= kMaxPanel.
+// ld n at R + i*sR; Rinv row-major ld n at Rinv + i*sRi); n <= kMaxPanel;
+// for n > kLdsPanel, gwork holds batch * chol_scratch_doubles(n) doubles.
 hipError_t launch_tri_inv(const double *R, int n, int64_t sR, double *Rinv, int64_t sRi, int batch,
-                          hipStream_t s);
+                          hipStream_t s, double *gwork = nullptr);
 
 // The n x n part of the QR adjoint, per matrix i of the batch:
 //   C = copyltu(R dR^T - P) with P = dQ^T Q taken from T = S^T dQ (upper

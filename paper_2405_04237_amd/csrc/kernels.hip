@@ -1074,7 +1074,10 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
     sCin = sC;
   }
   const int slabs = (q + kTile - 1) / kTile;
-  const int wc = slabs >= 4 ? 4 : (slabs >= 2 ? 2 : 1);
+  // a product without input C (Q = X U^{-1}, possibly in place) keeps all of
+  // a row tile's columns in one workgroup: three slabs take all four
+  // column waves (one idle) rather than two column groups
+  const int wc = (slabs >= 4 || (!subtract && slabs == 3)) ? 4 : (slabs >= 2 ? 2 : 1);
   const int wr = 4 / wc;
   const int ncg = (slabs + wc - 1) / wc;
   if (!subtract && !upper_y && C2 == nullptr && p <= kYsMaxK && p % 16 == 0 && psplit % 16 == 0 &&
@@ -1108,7 +1111,7 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
       static const hipError_t attr = [] {
         const hipError_t e = hipFuncSetAttribute((const void *)k_trsm<128>,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 kMaxPanel * kMaxPanel * (int)sizeof(double));
+                                                 kLdsPanel * kLdsPanel * (int)sizeof(double));
         if (e != hipSuccess) return e;
         return hipFuncSetAttribute((const void *)k_trsm<64>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1369,15 +1372,95 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double *__restr
   }
 }
 
+// Panels wider than kLdsPanel: the same factorisation and inverse with the
+// matrix (padded with the identity to order 256) in the device scratch G,
+// one 512-thread workgroup (wide_cholesky / wide_upper_inverse).
+constexpr int kWideThreads = 512;
+
+__global__ __launch_bounds__(kWideThreads) void k_chol_inv_wide(
+    const double *__restrict__ W, int w, double *__restrict__ uout, double *__restrict__ rblk,
+    int64_t ldr, double *__restrict__ uinv, double *__restrict__ G, int *info, int col0,
+    double skip_tol, int *skip) {
+  extern __shared__ double S[];
+  __shared__ int flag;
+  __shared__ double red[kWideThreads];
+  if (*info) return;
+  const int tid = threadIdx.x, nt = blockDim.x, wp = blocked_order(w);
+  if (skip) {
+    // ||W - I||_F in a fixed order, as k_chol_inv
+    double acc = 0.0;
+    for (int e = tid; e < w * w; e += nt) {
+      const int i = e / w, j = e % w;
+      if (i <= j) {
+        const double v = W[e] - (i == j ? 1.0 : 0.0);
+        acc += (i == j ? 1.0 : 2.0) * v * v;
+      }
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (int h = kWideThreads / 2; h > 0; h >>= 1) {
+      if (tid < h) red[tid] += red[tid + h];
+      __syncthreads();
+    }
+    const bool near = sqrt(red[0]) <= skip_tol;
+    if (tid == 0) *skip = near ? 1 : 0;
+    if (near) {
+      for (int e = tid; e < w * w; e += nt) {
+        const int i = e / w, j = e % w;
+        const double u = (i == j) ? 1.0 : 0.0;
+        if (uout) uout[e] = u;
+        if (rblk) rblk[i + (int64_t)j * ldr] = u;
+      }
+      const int ldu = (int)padded_ld(w);
+      for (int e = tid; e < w * ldu; e += nt) uinv[e] = (e / ldu == e % ldu) ? 1.0 : 0.0;
+      return;
+    }
+  }
+  for (int e = tid; e < wp * wp; e += nt) {
+    const int i = e / wp, j = e % wp;
+    G[e] = (i < w && j < w) ? ((i <= j) ? W[i * w + j] : 0.0) : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  const int fail = wide_cholesky(G, wp, S, &flag);
+  if (fail) {
+    if (tid == 0) atomicCAS(info, 0, col0 + fail);
+    return;
+  }
+  for (int e = tid; e < w * w; e += nt) {
+    const int i = e / w, j = e % w;
+    const double u = (i <= j) ? G[(int64_t)i * wp + j] : 0.0;
+    if (uout) uout[e] = u;
+    if (rblk) rblk[i + (int64_t)j * ldr] = u;
+  }
+  __syncthreads();
+  wide_upper_inverse(G, wp, S);
+  const int ldu = (int)padded_ld(w);
+  for (int e = tid; e < w * ldu; e += nt) {
+    const int i = e / ldu, c = e % ldu;
+    uinv[e] = (c < i || c >= w) ? 0.0 : G[(int64_t)i * wp + c];
+  }
+}
+
 hipError_t launch_chol_inv(const double *W, int w, double *uout, double *rblk, int64_t ldr,
                            double *uinv, int *info, int col0, hipStream_t s, double skip_tol,
-                           int *skip) {
+                           int *skip, double *gwork) {
   if (w < 1 || w > kMaxPanel) return hipErrorInvalidValue;
   const int wp = blocked_order(w);
+  if (w > kLdsPanel) {
+    if (!gwork) return hipErrorInvalidValue;
+    const size_t lds = (size_t)wide_lds_doubles(wp) * sizeof(double);
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)k_chol_inv_wide, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)((size_t)wide_lds_doubles(kMaxPanel) * sizeof(double)));
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(k_chol_inv_wide, dim3(1), dim3(kWideThreads), lds, s, W, w, uout, rblk,
+                       ldr, uinv, gwork, info, col0, skip_tol, skip);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)blocked_lds_doubles(wp) * sizeof(double);
   static const hipError_t attr = hipFuncSetAttribute(
       (const void *)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
-      (int)((size_t)blocked_lds_doubles(kMaxPanel) * sizeof(double)));
+      (int)((size_t)blocked_lds_doubles(kLdsPanel) * sizeof(double)));
   if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kCholThreads), lds, s, W, w, uout, rblk, ldr, uinv,
                      info, col0, skip_tol, skip);
@@ -1409,14 +1492,47 @@ __global__ __launch_bounds__(kCholThreads) void k_tri_inv(const double *__restri
   }
 }
 
+// Rinv = R^{-1} for n > kLdsPanel: R padded with the identity into the
+// device scratch G (order 256, one per matrix), wide_upper_inverse there.
+__global__ __launch_bounds__(kWideThreads) void k_tri_inv_wide(const double *__restrict__ R, int n,
+                                                               int64_t sR, double *__restrict__ Rinv,
+                                                               int64_t sRi, double *__restrict__ G) {
+  extern __shared__ double S[];
+  const int tid = threadIdx.x, nt = blockDim.x, wp = blocked_order(n);
+  R += blockIdx.x * sR;
+  Rinv += blockIdx.x * sRi;
+  G += (int64_t)blockIdx.x * wp * wp;
+  for (int e = tid; e < wp * wp; e += nt) {
+    const int i = e / wp, j = e % wp;
+    G[e] = (i < n && j < n) ? ((i <= j) ? R[i + (int64_t)j * n] : 0.0) : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  wide_upper_inverse(G, wp, S);
+  for (int e = tid; e < n * n; e += nt) {
+    const int i = e / n, c = e % n;
+    Rinv[e] = (c < i) ? 0.0 : G[(int64_t)i * wp + c];
+  }
+}
+
 hipError_t launch_tri_inv(const double *R, int n, int64_t sR, double *Rinv, int64_t sRi, int batch,
-                          hipStream_t s) {
+                          hipStream_t s, double *gwork) {
   if (n < 1 || n > kMaxPanel) return hipErrorInvalidValue;
   const int wp = blocked_order(n);
+  if (n > kLdsPanel) {
+    if (!gwork) return hipErrorInvalidValue;
+    const size_t lds = (size_t)wide_lds_doubles(wp) * sizeof(double);
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)k_tri_inv_wide, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)((size_t)wide_lds_doubles(kMaxPanel) * sizeof(double)));
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(k_tri_inv_wide, dim3((unsigned)batch), dim3(kWideThreads), lds, s, R, n, sR,
+                       Rinv, sRi, gwork);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)blocked_lds_doubles(wp) * sizeof(double);
   static const hipError_t attr = hipFuncSetAttribute(
       (const void *)k_tri_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
-      (int)((size_t)blocked_lds_doubles(kMaxPanel) * sizeof(double)));
+      (int)((size_t)blocked_lds_doubles(kLdsPanel) * sizeof(double)));
   if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL(k_tri_inv, dim3((unsigned)batch), dim3(kCholThreads), lds, s, R, n, sR, Rinv,
                      sRi);

@@ -24,7 +24,7 @@ RES_TOL = 1e-14
 
 
 def candidates(n: int, schedule: str):
-    c = [b for b in (16, 32, 64, 128) if b <= min(n, _lib.CQR_MAX_PANEL)]
+    c = [b for b in (16, 32, 64, 128, 256) if b <= min(n, _lib.CQR_MAX_PANEL)]
     return c or [n]
 
 

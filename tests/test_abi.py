@@ -67,7 +67,7 @@ def test_workspace_and_panel_queries(lib):
     for n in (1, 16, 64, 100, 256, 1024):
         for s in (_lib.SCHED_MOD, _lib.SCHED_ORIG):
             b = _lib.default_panel(1 << 20, n, s)
-            assert 1 <= b <= min(n, _lib.CQR_MAX_PANEL)
+            assert 1 <= b <= min(n, 128)  # the default stays within the LDS Cholesky
     # sCQR3 is one whole-matrix panel (b is ignored) and keeps R1, R2 like ORIG
     assert _lib.default_panel(1 << 20, 100, _lib.SCHED_SCQR3) == 100
     assert (_lib.workspace_bytes(1 << 20, 128, 0, _lib.SCHED_SCQR3)
@@ -87,8 +87,8 @@ FAKE = C.c_void_p(4096)  # never dereferenced: every call below fails validation
     (100, 10, -2, 100, True, 0, _lib.CQR_ERR_ARG),     # b < 0
     (100, 10, 4, 100, False, 0, _lib.CQR_ERR_ARG),     # null pointers
     (100, 10, 4, 100, True, 3, _lib.CQR_ERR_ARG),      # bad schedule
-    (1000, 300, 200, 1000, True, 0, _lib.CQR_ERR_UNSUPPORTED),  # b > CQR_MAX_PANEL
-    (1000, 129, 0, 1000, True, 2, _lib.CQR_ERR_UNSUPPORTED),    # sCQR3 with n > CQR_MAX_PANEL
+    (1000, 300, 290, 1000, True, 0, _lib.CQR_ERR_UNSUPPORTED),  # b > CQR_MAX_PANEL
+    (1000, 257, 0, 1000, True, 2, _lib.CQR_ERR_UNSUPPORTED),    # sCQR3 with n > CQR_MAX_PANEL
     (100, 10, -1, 100, True, 2, _lib.CQR_ERR_ARG),              # sCQR3 still rejects b < 0
 ])
 def test_argument_errors(lib, m, n, b, lda, ptrs, sched, expect):
@@ -137,7 +137,7 @@ def test_batched_plan_argument_errors(lib):
     ((2, 100, 10, FAKE, None, 100, 999, FAKE, FAKE, FAKE, FAKE), _lib.CQR_ERR_ARG),   # stride < lda n
     ((1, 100, 10, None, None, 100, 1000, FAKE, FAKE, FAKE, FAKE), _lib.CQR_ERR_ARG),  # no Q and no A
     ((1, 100, 10, FAKE, None, 100, 1000, None, FAKE, FAKE, FAKE), _lib.CQR_ERR_ARG),  # no R
-    ((1, 1000, 200, FAKE, None, 1000, 200000, FAKE, FAKE, FAKE, FAKE), _lib.CQR_ERR_UNSUPPORTED),
+    ((1, 1000, 257, FAKE, None, 1000, 257000, FAKE, FAKE, FAKE, FAKE), _lib.CQR_ERR_UNSUPPORTED),
 ])
 def test_backward_argument_errors(lib, args, expect):
     bsz, m, n, q, a, lda, stride, r, dq, dr, da = args
@@ -150,3 +150,4 @@ def test_backward_workspace_query(lib):
     assert _lib.backward_workspace_bytes(262144, 128, 1) > 0
     assert _lib.backward_workspace_bytes(32768, 64, 64) > _lib.backward_workspace_bytes(32768, 64, 1)
     assert _lib.backward_workspace_bytes(10, 20, 1) == 0
+

@@ -145,6 +145,32 @@ int cqr_factor(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
 int cqr_factor_ex(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
                   double *Q, double *R, void *stream, const cqr_options *opt);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * cqr_factor_ex with a caller workspace, but the workspace is a fixed
+ * CQR_NOALLOC_SCRATCH_BYTES array in the library's device code, one per
+ * device, created when the library's device code is loaded on that device
+ * and held until the process ends. The call allocates nothing (no hipMalloc
+ * or hipFree, no events; per-kernel profiling does not bracket it), and the
+ * caller still owns A, Q, R and the info word.
+ *   schedule  enum cqr_schedule; the look-ahead and adaptive options are off.
+ *   d_info    device int, required (NULL is CQR_ERR_ARG); 0 or the 1-based
+ *             breakdown column, as for cqr_factor_ex.
+ * Sizes whose in-place workspace (cqr_workspace_bytes(m, n, b, schedule))
+ * exceeds CQR_NOALLOC_SCRATCH_BYTES return CQR_ERR_WORKSPACE before any
+ * device work. An aliasing lda (a multiple of 1024 doubles) is factored in
+ * place, never through a staging copy. Results are bitwise those of
+ * cqr_factor_ex with the same arguments and a caller workspace of that size.
+ * Every call on a device shares that device's array, and nothing in it needs
+ * to start at zero (each call writes every region before reading it): calls
+ * that overlap in time on one device, on any streams, race and give
+ * undefined results. The first call on a device looks up the array's device
+ * address (hipGetSymbolAddress) and must not be made during stream capture;
+ * later calls may be captured. */
+#define CQR_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int cqr_factor_noalloc(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
+                       double *Q, double *R, int schedule, int *d_info, void *stream);
+
 /* Bytes of device workspace cqr_factor_ex needs for these sizes and leading
  * dimension (host arithmetic only; 0 for invalid sizes, lda < m included).
  * The info word is not included. When lda is a multiple of 1024 doubles the

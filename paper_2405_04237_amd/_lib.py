@@ -18,6 +18,7 @@ CQR_ERR_NOMEM = -3
 CQR_ERR_WORKSPACE = -4
 CQR_ERR_UNSUPPORTED = -5
 CQR_MAX_PANEL = 256
+CQR_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 SCHED_MOD = 0
 SCHED_ORIG = 1
@@ -39,6 +40,7 @@ class CqrOptions(C.Structure):
 SIGNATURES = {
     "cqr_factor": (C.c_int, [_I64, _I64, _I64, _DP, _I64, _DP, _DP, _VP]),
     "cqr_factor_ex": (C.c_int, [_I64, _I64, _I64, _DP, _I64, _DP, _DP, _VP, C.POINTER(CqrOptions)]),
+    "cqr_factor_noalloc": (C.c_int, [_I64, _I64, _I64, _DP, _I64, _DP, _DP, C.c_int, _VP, _VP]),
     "cqr_workspace_bytes": (C.c_size_t, [_I64, _I64, _I64, C.c_int]),
     "cqr_workspace_bytes_ld": (C.c_size_t, [_I64, _I64, _I64, _I64, C.c_int]),
     "cqr_default_panel": (C.c_int64, [_I64, _I64, C.c_int]),
@@ -109,6 +111,11 @@ def factor_ex(m, n, b, a_ptr, lda, q_ptr, r_ptr, stream, schedule, info_ptr, ws_
 
 def factor(m, n, b, a_ptr, lda, q_ptr, r_ptr, stream):
     return int(lib().cqr_factor(m, n, b, a_ptr, lda, q_ptr, r_ptr, stream))
+
+
+def factor_noalloc(m, n, b, a_ptr, lda, q_ptr, r_ptr, schedule, info_ptr, stream):
+    return int(lib().cqr_factor_noalloc(m, n, b, a_ptr, lda, q_ptr, r_ptr, schedule, info_ptr,
+                                        stream))
 
 
 def backward_workspace_bytes(m: int, n: int, batch: int = 1) -> int:

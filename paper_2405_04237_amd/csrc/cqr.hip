@@ -212,6 +212,9 @@ struct Acc {
   double ms = 0, flops = 0, bytes = 0;
 };
 bool g_prof = false;
+// Set while cqr_factor_noalloc runs on this thread: its launches are never
+// bracketed by timing events (creating an event may allocate).
+thread_local bool t_no_events = false;
 unsigned g_prof_mask = ~0u;  // kernel classes bracketed while profiling is on
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
@@ -230,7 +233,7 @@ hipEvent_t pool_get() {
 
 template <class F>
 hipError_t timed(hipStream_t s, int kind, double flops, double bytes, F &&f) {
-  if (!g_prof || !(g_prof_mask & (1u << kind))) return f();
+  if (!g_prof || t_no_events || !(g_prof_mask & (1u << kind))) return f();
   std::lock_guard<std::mutex> lk(g_mu);
   hipEvent_t a = pool_get(), b = pool_get();
   if (!a || !b) return hipErrorOutOfMemory;
@@ -684,6 +687,61 @@ int cqr_factor(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda, do
   return cqr_factor_ex(m, n, b, A, lda, Q, R, stream, nullptr);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------- no-allocation scratch
+// The workspace of cqr_factor_noalloc: a fixed array in the library's device
+// code, one copy per device, created when the code is loaded on that device
+// and held until the process ends. In host code `scratch` names a host-side
+// stand-in, not device memory: host code uses only the device address
+// hipGetSymbolAddress returns for the current device (g_scratch).
+static __device__ __align__(256) char scratch[CQR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void *g_scratch[kMaxDevices];  // device address of `scratch` per device (null until set up)
+std::mutex g_scratch_mu;
+
+// The current device's address of `scratch`, looked up on its first use.
+hipError_t scratch_address(void **out) {
+  int dev = 0;
+  CQR_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    CQR_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
+int cqr_factor_noalloc(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda, double *Q,
+                       double *R, int schedule, int *d_info, void *stream) {
+  const int st = check_args(m, n, b, A, lda, Q, R, schedule);
+  if (st != CQR_OK) return st;
+  if (!d_info || misaligned(d_info, 4)) return CQR_ERR_ARG;
+  // the in-place layout only: a staging copy of an aliasing lda would need
+  // lda * n more doubles
+  const Layout plain = make_layout(m, n, effective_panel(m, n, b, schedule), schedule, false);
+  if ((size_t)plain.total > (size_t)CQR_NOALLOC_SCRATCH_BYTES) return CQR_ERR_WORKSPACE;
+  void *ws = nullptr;
+  if (scratch_address(&ws) != hipSuccess) return CQR_ERR_HIP;
+  cqr_options opt{};
+  opt.schedule = schedule;
+  opt.d_info = d_info;
+  opt.workspace = ws;
+  opt.workspace_bytes = (size_t)plain.total;
+  t_no_events = true;
+  const int rc = cqr_factor_ex(m, n, b, A, lda, Q, R, stream, &opt);
+  t_no_events = false;
+  return rc;
+}
 
 int cqr_get_info(void *stream, int *info) {
   if (!info) return CQR_ERR_ARG;

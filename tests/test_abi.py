@@ -151,3 +151,21 @@ def test_backward_workspace_query(lib):
     assert _lib.backward_workspace_bytes(32768, 64, 64) > _lib.backward_workspace_bytes(32768, 64, 1)
     assert _lib.backward_workspace_bytes(10, 20, 1) == 0
 
+
+def test_noalloc_argument_errors(lib):
+    """cqr_factor_noalloc validates before it touches the device: the usual
+    argument errors, a missing info word, and sizes whose workspace exceeds
+    its fixed array."""
+    f = _lib.factor_noalloc
+    assert f(10, 20, 4, FAKE, 10, FAKE, FAKE, 0, FAKE, None) == _lib.CQR_ERR_ARG     # m < n
+    assert f(100, 10, 4, None, 100, FAKE, FAKE, 0, FAKE, None) == _lib.CQR_ERR_ARG   # null A
+    assert f(100, 10, 4, FAKE, 100, FAKE, FAKE, 0, None, None) == _lib.CQR_ERR_ARG   # no info
+    assert f(100, 10, 4, FAKE, 100, FAKE, FAKE, 9, FAKE, None) == _lib.CQR_ERR_ARG   # schedule
+    big = (1 << 22, 1024, 128)
+    assert _lib.workspace_bytes(*big, _lib.SCHED_MOD) > _lib.CQR_NOALLOC_SCRATCH_BYTES
+    assert f(*big[:3], FAKE, big[0], FAKE, FAKE, 0, FAKE, None) == _lib.CQR_ERR_WORKSPACE
+    # the limit is the in-place workspace: an aliasing lda adds no staging room
+    m, n, b = 1 << 16, 64, 32
+    assert _lib.workspace_bytes(m, n, b, 0) <= _lib.CQR_NOALLOC_SCRATCH_BYTES
+    text = open(os.path.join(ROOT, "include", "cqr.h")).read()
+    assert re.search(r"#define CQR_NOALLOC_SCRATCH_BYTES \(\(size_t\)128 << 20\)", text)

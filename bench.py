@@ -512,6 +512,13 @@ def main():
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--schedule", default="mod", choices=["mod", "orig"])
     ap.add_argument("--b", type=int, default=0, help="panel width (0 = autotune)")
+    ap.add_argument("--update-tile", default="auto",
+                    choices=["auto", "slab", "wide", "narrow", "resident"],
+                    help="update kernel variant (auto: the autotuner's choice, or libcqr's "
+                         "default when --b is given)")
+    ap.add_argument("--proj-tile", default="auto", choices=["auto", "wide", "narrow"])
+    ap.add_argument("--no-tile-tune", action="store_true",
+                    help="tune the panel width only (default tile variants)")
     ap.add_argument("--cpu-rows", type=int, default=1 << 18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
@@ -559,20 +566,30 @@ def main():
     torch.cuda.synchronize()
     log(f"generated in {time.perf_counter() - t0:.1f} s")
 
+    ut, pt = args.update_tile, args.proj_tile
     if args.b:
         b, table = args.b, None
     else:
-        b, table = tune.tune(a, args.schedule, cands=list(w["b_cands"]), log=log)
-        if b is None:
+        cfg, table = tune.tune(a, args.schedule, cands=list(w["b_cands"]), log=log,
+                               tiles=not args.no_tile_tune)
+        if cfg is None:
             log("no candidate panel width met the accuracy gate; using the narrowest")
             b = min(w["b_cands"])
+        else:
+            b = cfg["b"]
+            if ut == "auto":
+                ut = cfg["update_tile"]
+            if pt == "auto":
+                pt = cfg["proj_tile"]
     ws = cqr.Workspace(m, n, b, args.schedule, dev, lda=a.stride(1))
     q = cqr.empty_colmajor(m, n, dev, ld=a.stride(1))
     r = cqr.empty_colmajor(n, n, dev)
     stream = torch.cuda.current_stream(dev)
+    log(f"configuration: b={b} update_tile={ut} proj_tile={pt}")
 
     def step():
-        cqr.qr(a, b=b, schedule=args.schedule, out=(q, r), workspace=ws, check=False)
+        cqr.qr(a, b=b, schedule=args.schedule, out=(q, r), workspace=ws, check=False,
+               update_tile=ut, proj_tile=pt)
 
     # warmup with every kernel class bracketed by HIP events: the per-kernel
     # table, and which class dominates the step
@@ -650,7 +667,8 @@ def main():
                 torch.cuda.synchronize()
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-            cqr.qr(a2, b=b, schedule=args.schedule, out=(q, r), workspace=ws2, check=False)
+            cqr.qr(a2, b=b, schedule=args.schedule, out=(q, r), workspace=ws2, check=False,
+                   update_tile=ut, proj_tile=pt)
         e1.record(stream)
         torch.cuda.synchronize()
         ms2 = e0.elapsed_time(e1) / k2
@@ -669,7 +687,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "lda": lda,
                    "kappa": kappa if args.input == "kappa" else None, "input": args.input, "b": b,
-                   "schedule": "mCQR2GS" if args.schedule == "mod" else "CQR2GS"},
+                   "schedule": "mCQR2GS" if args.schedule == "mod" else "CQR2GS",
+                   "update_tile": ut, "proj_tile": pt},
         "orthogonality": orth, "orthogonality_normalised": None if orth is None else orth / math.sqrt(n), "residual": res,
         "info": info, "wall_s": round(wall, 3), "roofline": roof, "step_roofline": step_roof,
         "kernels": kern, "kernels_note": "per-class HIP-event times from the warmup steps, except the roofline kernel (timed region)",

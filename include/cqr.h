@@ -117,7 +117,38 @@ typedef struct cqr_options {
                               (no synchronisation); the accuracy bounds are
                               kept, and well-conditioned panels cost fewer
                               passes. 0: every repetition runs. */
+  int update_tile;         /* kernel variant of the trailing updates
+                              A_rest -= Q_j Y and Qt -= Q_{1:j-1} Z (enum
+                              cqr_tile; the panel width b is the paper's
+                              tuning knob, section "CholeskyQR2 with
+                              Gram-Schmidt", and these are the GPU's): every
+                              variant computes each entry with the same
+                              operations in the same order, so the choice
+                              changes speed only, never the bits. A variant
+                              that does not apply to a shape or alignment
+                              falls back to CQR_TILE_AUTO. */
+  int proj_tile;           /* kernel variant of the projections
+                              Y = Q_j^T A_rest and Z = Q_{1:j-1}^T Qt (enum
+                              cqr_tile: CQR_TILE_WIDE or CQR_TILE_NARROW;
+                              same bits either way). */
 } cqr_options;
+
+/* Kernel variants of the streaming products (cqr_options.update_tile and
+ * proj_tile); values outside the enum return CQR_ERR_ARG. */
+enum cqr_tile {
+  CQR_TILE_AUTO = 0,   /* the library's default for the shape */
+  CQR_TILE_SLAB = 1,   /* update: 64-column slab of Y in LDS, rows streamed
+                          (inner dimension <= 128) */
+  CQR_TILE_WIDE = 2,   /* 64 x 128 output tile per wave, accumulators held
+                          over the whole inner dimension (update and
+                          projection) */
+  CQR_TILE_NARROW = 3, /* update: 32 x 64 tiles, four waves per workgroup;
+                          projection: 64 x 64 tiles */
+  CQR_TILE_RESIDENT = 4 /* update: each wave's rows of Q_j held in registers
+                           while it sweeps every 64-column slab of the
+                           update (Q_j read once), inner dimension <= 128
+                           and a multiple of 16 */
+};
 
 /* Tolerance of cqr_options.adaptive (a Frobenius norm). */
 #define CQR_ADAPTIVE_TOL 1e-14

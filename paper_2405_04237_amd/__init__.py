@@ -72,7 +72,8 @@ class Workspace:
 
 
 def qr(a, b: int = 0, schedule: str = "mod", check: bool = True, out=None,
-       workspace: Workspace | None = None, lookahead: bool = False, adaptive: bool = False):
+       workspace: Workspace | None = None, lookahead: bool = False, adaptive: bool = False,
+       update_tile: str = "auto", proj_tile: str = "auto"):
     """Thin QR of a tall-and-skinny FP64 matrix: returns (Q, R).
 
     schedule "mod" = mCQR2GS (Algorithm 9), "orig" = CQR2GS (Algorithm 7),
@@ -81,7 +82,10 @@ def qr(a, b: int = 0, schedule: str = "mod", check: bool = True, out=None,
     each mCQR2GS panel's chain on a side stream, overlapped with the trailing
     update (bitwise the same result). adaptive=True leaves out a panel's
     repeated CholeskyQR or re-orthogonalisation update when it is within
-    libcqr's tolerance of doing nothing (mCQR2GS only). With check=True the call waits
+    libcqr's tolerance of doing nothing (mCQR2GS only). update_tile and
+    proj_tile pick the kernel variant of the updates ("slab", "resident",
+    "wide", "narrow") and projections ("wide", "narrow"); "auto" is libcqr's
+    default, and every variant gives the same bits. With check=True the call waits
     for the device and raises Breakdown if a Cholesky pivot failed;
     otherwise the caller reads ``workspace.info``.
     """
@@ -89,6 +93,8 @@ def qr(a, b: int = 0, schedule: str = "mod", check: bool = True, out=None,
     _check_input(a)
     if schedule not in SCHEDULES:
         raise ValueError(f"schedule must be one of {sorted(SCHEDULES)}")
+    if update_tile not in _lib.TILES or proj_tile not in _lib.TILES:
+        raise ValueError(f"tile variants must be one of {sorted(_lib.TILES)}")
     a = as_colmajor(a)
     m, n = a.shape
     lda = a.stride(1)
@@ -104,7 +110,8 @@ def qr(a, b: int = 0, schedule: str = "mod", check: bool = True, out=None,
     stream = torch.cuda.current_stream(a.device).cuda_stream
     st = _lib.factor_ex(m, n, b, a.data_ptr(), lda, q.data_ptr(), r.data_ptr(), stream,
                         SCHEDULES[schedule], workspace.info.data_ptr(),
-                        workspace.buf.data_ptr(), workspace.bytes, lookahead, adaptive)
+                        workspace.buf.data_ptr(), workspace.bytes, lookahead, adaptive,
+                        _lib.TILES[update_tile], _lib.TILES[proj_tile])
     _lib.check(st, "cqr_factor_ex")
     if check:
         col = int(workspace.info.item())

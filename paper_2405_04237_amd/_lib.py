@@ -34,7 +34,8 @@ _I64, _VP, _DP = C.c_int64, C.c_void_p, C.c_void_p
 
 class CqrOptions(C.Structure):
     _fields_ = [("schedule", C.c_int), ("d_info", C.c_void_p), ("workspace", C.c_void_p),
-                ("workspace_bytes", C.c_size_t), ("lookahead", C.c_int), ("adaptive", C.c_int)]
+                ("workspace_bytes", C.c_size_t), ("lookahead", C.c_int), ("adaptive", C.c_int),
+                ("update_tile", C.c_int), ("proj_tile", C.c_int)]
 
 
 SIGNATURES = {
@@ -102,10 +103,13 @@ def default_panel(m: int, n: int, schedule: int) -> int:
     return int(lib().cqr_default_panel(m, n, schedule))
 
 
+TILES = {"auto": 0, "slab": 1, "wide": 2, "narrow": 3, "resident": 4}
+
+
 def factor_ex(m, n, b, a_ptr, lda, q_ptr, r_ptr, stream, schedule, info_ptr, ws_ptr, ws_bytes,
-              lookahead=False, adaptive=False):
+              lookahead=False, adaptive=False, update_tile=0, proj_tile=0):
     opt = CqrOptions(schedule, info_ptr, ws_ptr, ws_bytes, 1 if lookahead else 0,
-                     1 if adaptive else 0)
+                     1 if adaptive else 0, int(update_tile), int(proj_tile))
     return int(lib().cqr_factor_ex(m, n, b, a_ptr, lda, q_ptr, r_ptr, stream, C.byref(opt)))
 
 

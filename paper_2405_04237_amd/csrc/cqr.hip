@@ -261,6 +261,7 @@ struct Run {
   int64_t part_elems;
   double *Qout;  // staged runs: the caller's Q, written by each panel's final step
   int64_t ldq;
+  int upd_tile, proj_tile;  // kernel variants of the updates and projections
 };
 
 void plan_chunks(const Run &r, int64_t tiles, int64_t pq, int64_t *rc, int64_t *nch) {
@@ -317,10 +318,13 @@ hipError_t step_trsm(Run &r, const double *X, double *Qo, int64_t ld, int w, int
 hipError_t step_proj(Run &r, const double *Qp, int64_t ld, int p, const double *Z, int q,
                      double *rblk, int64_t ldr) {
   int64_t rc, nch;
+  // the split-m plan (and with it the order of every sum) is that of the
+  // default tiles whatever variant runs, so the variants agree bit for bit
   const int64_t tiles = cqr::tn_tiles(false, p, q);
   plan_chunks(r, tiles, (int64_t)p * q, &rc, &nch);
   CQR_TRY(timed(r.s, CQR_K_PROJ, 2.0 * r.m * p * q, 8.0 * r.m * (p + q), [&] {
-    return cqr::launch_tn(false, r.m, p, q, Qp, ld, Z, ld, r.part, rc, nch, r.info, r.s);
+    return cqr::launch_tn(false, r.m, p, q, Qp, ld, Z, ld, r.part, rc, nch, r.info, r.s, 1, 0, 0,
+                          0, r.proj_tile);
   }));
   return timed(r.s, CQR_K_REDUCE, double(nch) * p * q, 8.0 * (nch + 1) * p * q, [&] {
     return cqr::launch_reduce(false, r.part, nch, p, q, r.Y, cqr::padded_ld(q), rblk, ldr, true,
@@ -337,7 +341,7 @@ hipError_t step_update_y(Run &r, const double *Qp, int64_t ld, int p, const doub
   const int *sk = (Zi == Zo) ? skip : nullptr;
   return timed(r.s, kind, 2.0 * r.m * p * q, 8.0 * r.m * (p + 2.0 * q), [&] {
     return cqr::launch_nn(true, false, r.m, p, q, Qp, ld, Ym, ldy, Zi, ld, Zo, ld, r.info, r.s,
-                          nullptr, 0, 0, 1, 0, 0, 0, 0, 0, nullptr, 0, sk);
+                          nullptr, 0, 0, 1, 0, 0, 0, 0, 0, nullptr, 0, sk, r.upd_tile);
   });
 }
 
@@ -593,6 +597,9 @@ int cqr_factor_ex(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
   const int schedule = opt ? opt->schedule : CQR_SCHED_MOD;
   const int st = check_args(m, n, b, A, lda, Q, R, schedule);
   if (st != CQR_OK) return st;
+  if (opt && (opt->update_tile < CQR_TILE_AUTO || opt->update_tile > CQR_TILE_RESIDENT ||
+              opt->proj_tile < CQR_TILE_AUTO || opt->proj_tile > CQR_TILE_NARROW))
+    return CQR_ERR_ARG;
   const int64_t be = effective_panel(m, n, b, schedule);
   // staged when lda aliases and the workspace has room (else factored in place)
   Layout lay = make_layout(m, n, be, schedule, aliasing_ld(lda));
@@ -650,6 +657,8 @@ int cqr_factor_ex(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda,
   r.zskip = (int *)(ws + lay.flags);
   r.cskip = r.zskip + 1;
   r.adaptive = (opt && opt->adaptive && schedule == CQR_SCHED_MOD) ? CQR_ADAPTIVE_TOL : 0.0;
+  r.upd_tile = opt ? opt->update_tile : CQR_TILE_AUTO;
+  r.proj_tile = opt ? opt->proj_tile : CQR_TILE_AUTO;
   std::unique_lock<std::mutex> side_lock;
   if (opt && opt->lookahead && schedule == CQR_SCHED_MOD && r.Yz && be < n) {
     DevState *ds = nullptr;

@@ -13,6 +13,17 @@ constexpr int kNnWaves = 4;      // waves per workgroup of the row-streaming GEM
 constexpr int kLdsPanel = 128;   // largest panel width the LDS Cholesky holds
 constexpr int kMaxPanel = 256;   // widest panel (above kLdsPanel: through device memory)
 
+// Kernel variants of the streaming products (the tile fields of
+// cqr_options, same values): kTileAuto = the library's default for the
+// shape; kTileSlab = update with a 64-column slab of Y staged in LDS (inner
+// dimension <= 128); kTileWide = 64 x 128 output tiles per wave (update:
+// k_nn_wide, projection: k_tn_wide); kTileNarrow = 32 x 64 update tiles
+// (k_nn) or 64 x 64 projection tiles (k_tn); kTileResident = update with each
+// wave's rows of L held in registers across every slab of C (inner
+// dimension <= 128, a multiple of 16). A variant that does not apply to a
+// shape or alignment falls back to the default.
+enum TileVariant { kTileAuto = 0, kTileSlab = 1, kTileWide = 2, kTileNarrow = 3, kTileResident = 4 };
+
 // Doubles of device scratch the Cholesky / inverse of a w x w matrix needs
 // (0 for w <= kLdsPanel; the identity-padded order-256 matrix otherwise).
 inline int64_t chol_scratch_doubles(int w) { return w > kLdsPanel ? int64_t(kMaxPanel) * kMaxPanel : 0; }
@@ -24,15 +35,17 @@ inline int64_t chol_scratch_doubles(int w) { return w > kLdsPanel ? int64_t(kMax
 // Rt may differ (a Gram matrix passes the same matrix twice).
 // batch > 1: `batch` independent problems of the same shape, operand i at
 // base + i * stride (strides in doubles).
+// tile (single-matrix projections): kTileNarrow keeps the 64 x 64 tiles
+// where the 64 x 128 ones would be used (same bits either way).
 hipError_t launch_tn(bool gram, int64_t m, int p, int q, const double *L, int64_t ldl,
                      const double *Rt, int64_t ldr, double *part, int64_t rc, int64_t nch,
                      const int *info, hipStream_t s, int batch = 1, int64_t sL = 0,
-                     int64_t sRt = 0, int64_t sPart = 0);
+                     int64_t sRt = 0, int64_t sPart = 0, int tile = kTileAuto);
 
 // Number of waves one row chunk of launch_tn occupies (its output tiles).
 // same: both operands are one matrix (a Gram matrix); with p = q = 128 that
-// selects the two-wave balanced Gram kernel.
-int64_t tn_tiles(bool gram, int p, int q, bool same = false);
+// selects the two-wave balanced Gram kernel. tile: as for launch_tn.
+int64_t tn_tiles(bool gram, int p, int q, bool same = false, int tile = kTileAuto);
 
 // Row-streaming product over all m rows, Y row-major p x q (leading dim ldy):
 //   subtract = false: C = L * Y   (Cin unused; C may alias L when q <= 256:
@@ -50,13 +63,15 @@ int64_t tn_tiles(bool gram, int p, int q, bool same = false);
 // skip (optional): the kernels do nothing when *skip != 0 at run time (the
 // caller has made the product an identity: Y = 0 for an update, Y = I for
 // an in-place product).
+// tile: the kernel variant of a single-matrix update (subtract = true,
+// batch = 1, no L2, no C2); every variant gives the same bits.
 hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const double *L,
                      int64_t ldl, const double *Y, int64_t ldy, const double *Cin, int64_t ldci,
                      double *C, int64_t ldc, const int *info, hipStream_t s,
                      const double *L2 = nullptr, int64_t ldl2 = 0, int psplit = 0, int batch = 1,
                      int64_t sL = 0, int64_t sL2 = 0, int64_t sY = 0, int64_t sCin = 0,
                      int64_t sC = 0, double *C2 = nullptr, int64_t ldc2 = 0,
-                     const int *skip = nullptr);
+                     const int *skip = nullptr, int tile = kTileAuto);
 
 // True when launch_nn runs a single-matrix subtract = true product through
 // the short-inner-dimension kernel (Y staged in LDS); false: the general one.

@@ -425,26 +425,27 @@ __global__ __launch_bounds__(64) void k_tn_wide(int64_t m, int p, int q, const d
       }
 }
 
-// the wide tile is used for single-matrix projections that fill it
-static bool tn_use_wide(bool gram, int p, int q, int batch) {
-  return !gram && batch == 1 && p >= kTile && q >= 2 * kTile;
+// the wide tile is used for single-matrix projections that fill it, unless
+// the 64 x 64 tiles are asked for
+static bool tn_use_wide(bool gram, int p, int q, int batch, int tile) {
+  return !gram && batch == 1 && p >= kTile && q >= 2 * kTile && tile != kTileNarrow;
 }
 
 static bool tn_use_gram128(bool gram, int p, int q, int batch, bool same) {
   return gram && same && p == 128 && q == 128 && batch == 1;
 }
 
-int64_t tn_tiles(bool gram, int p, int q, bool same) {
+int64_t tn_tiles(bool gram, int p, int q, bool same, int tile) {
   const int tp = (p + kTile - 1) / kTile, tq = (q + kTile - 1) / kTile;
   if (tn_use_gram128(gram, p, q, 1, same)) return 2;
-  if (tn_use_wide(gram, p, q, 1)) return (int64_t)tp * ((q + 2 * kTile - 1) / (2 * kTile));
+  if (tn_use_wide(gram, p, q, 1, tile)) return (int64_t)tp * ((q + 2 * kTile - 1) / (2 * kTile));
   return gram ? (int64_t)tp * (tp + 1) / 2 : (int64_t)tp * tq;
 }
 
 hipError_t launch_tn(bool gram, int64_t m, int p, int q, const double *L, int64_t ldl,
                      const double *Rt, int64_t ldr, double *part, int64_t rc, int64_t nch,
                      const int *info, hipStream_t s, int batch, int64_t sL, int64_t sRt,
-                     int64_t sPart) {
+                     int64_t sPart, int tile) {
   const int tp = (p + kTile - 1) / kTile, tq = (q + kTile - 1) / kTile;
   const bool vec = (ldl % 2 == 0) && (ldr % 2 == 0) && ((uintptr_t)L % 16 == 0) &&
                    ((uintptr_t)Rt % 16 == 0) && (rc % 16 == 0) && (sL % 2 == 0) && (sRt % 2 == 0);
@@ -456,7 +457,7 @@ hipError_t launch_tn(bool gram, int64_t m, int p, int q, const double *L, int64_
       hipLaunchKernelGGL((k_gram128<false>), gg, dim3(64), 0, s, m, L, ldl, part, rc, info);
     return hipGetLastError();
   }
-  if (tn_use_wide(gram, p, q, batch)) {
+  if (tn_use_wide(gram, p, q, batch, tile)) {
     const int tqw = (q + 2 * kTile - 1) / (2 * kTile);
     const dim3 gw((unsigned)((int64_t)tp * tqw * nch));
     if (vec)
@@ -467,7 +468,7 @@ hipError_t launch_tn(bool gram, int64_t m, int p, int q, const double *L, int64_
                          tp, tqw, info);
     return hipGetLastError();
   }
-  const int64_t nb = tn_tiles(gram, p, q) * nch;
+  const int64_t nb = tn_tiles(gram, p, q, false, kTileNarrow) * nch;
   dim3 grid((unsigned)nb, (unsigned)batch), block(64);
 #define CQR_TN(U, V)                                                                             \
   hipLaunchKernelGGL((k_tn<U, V>), grid, block, 0, s, m, p, q, L, ldl, Rt, ldr, part, rc, tp, tq, \
@@ -686,6 +687,14 @@ __global__ __launch_bounds__(256, (RB == 2) ? 2 : 1) void k_nn(
 // ----------------------------------------------------------------------------
 constexpr int kUpdMaxK = 128;
 
+// Position in a 64-column LDS slab row of column j (0..63): each lane of the
+// update kernels reads its 4 consecutive columns 4 cl .. 4 cl + 3 as two
+// 16-byte halves, so the row is stored as the first halves of all 16 lanes
+// followed by the second halves. Each 16-byte read then covers consecutive
+// addresses across the lanes (no bank conflicts); the plain order made every
+// read a two-way conflict (lanes 32 bytes apart).
+__host__ __device__ constexpr int slab_pos(int j) { return ((j >> 1) & 1) * 32 + (j >> 2) * 2 + (j & 1); }
+
 bool nn_short_k(int p, const double *L, int64_t ldl, const double *Cin, int64_t ldci,
                 const double *C, int64_t ldc) {
   return p <= kUpdMaxK && (ldl % 2 == 0) && (ldc % 2 == 0) && (ldci % 2 == 0) &&
@@ -708,12 +717,12 @@ __global__ __launch_bounds__(256, 2) void k_upd(int64_t m, int p, int q, const d
   const int pp = (p + 15) / 16 * 16;
   for (int e = threadIdx.x; e < pp * kTile; e += 256) {
     const int k = e / kTile, c = c0 + e % kTile;
-    ys[e] = (k < p && c < q) ? Y[(int64_t)k * ldy + c] : 0.0;
+    ys[k * kTile + slab_pos(e % kTile)] = (k < p && c < q) ? Y[(int64_t)k * ldy + c] : 0.0;
   }
   __syncthreads();
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
-  const double *yl = ys + 4 * cl;  // this lane's 4 columns of the slab
+  const double *yl = ys + 2 * cl;  // this lane's 4 columns of the slab (two halves)
   const int nit = p / 16;  // full 16-wide k steps; a ragged p adds one masked step
 
   for (int64_t r0 = rb + 32 * wave; r0 < re; r0 += 128) {
@@ -745,7 +754,7 @@ __global__ __launch_bounds__(256, 2) void k_upd(int64_t m, int p, int q, const d
       for (int s = 0; s < 4; ++s) {
         const int k = kk + 4 * s + g;
         const double2 y0 = *reinterpret_cast<const double2 *>(yl + k * kTile);
-        const double2 y1 = *reinterpret_cast<const double2 *>(yl + k * kTile + 2);
+        const double2 y1 = *reinterpret_cast<const double2 *>(yl + k * kTile + 32);
         da[s][0] = y0.x;
         da[s][1] = y0.y;
         da[s][2] = y1.x;
@@ -827,6 +836,329 @@ __global__ __launch_bounds__(256, 2) void k_upd(int64_t m, int p, int q, const d
         }
       }
   }
+}
+
+// ----------------------------------------------------------------------------
+// k_upd_lr: the same update C = Cin + L Y (inner dimension p <= kUpdMaxK,
+// p % 16 == 0) with each wave's rows of L held in registers: k_upd re-reads
+// L for every 64-column slab of C (q / 64 times; at 2^22 rows, 128 inner x
+// 896 columns its HBM reads came to 1.38 x the compulsory bytes, at 4.6 TB/s
+// of traffic), here L is read once. One persistent 4-wave workgroup per CU
+// takes 128-row blocks (32 rows per wave; rows [0, mfull), mfull a multiple
+// of 128) and sweeps every slab of C for them: slab s + 1 of Y is copied
+// from global memory straight into the other half of a double-buffered LDS
+// slab (global_load_lds) and its Cin into registers while slab s is
+// multiplied, so only the first slab of a row block waits for memory. Lane
+// maps, and the order of every sum (Cin first, then k ascending in groups of
+// four), are those of k_upd, so the two kernels agree bit for bit.
+// ----------------------------------------------------------------------------
+constexpr int kLrRows = 128;  // rows per block (4 waves x 32)
+
+__global__ __launch_bounds__(256, 1) void k_upd_lr(int64_t mfull, int p, int q, const double *L,
+                                                   int64_t ldl, const double *__restrict__ Y,
+                                                   int64_t ldy, const double *Cin, int64_t ldci,
+                                                   double *C, int64_t ldc,
+                                                   const int *__restrict__ info,
+                                                   const int *__restrict__ skip) {
+  // the two halves of the double-buffered Y slab ([p][64] each, row-major)
+  // are separate arrays, so that the compiler can tell the copy into one from
+  // the reads of the other and does not wait for the copy before reading
+  __shared__ double ys0[kUpdMaxK * kTile];
+  __shared__ double ys1[kUpdMaxK * kTile];
+  if (*info || (skip && *skip)) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const int nk = p / 16;
+  const int nslab = (q + kTile - 1) / kTile;
+  const int64_t nblk = mfull / kLrRows;
+
+  // Y slab sl -> LDS: each instruction moves two 64-column rows (16 bytes
+  // per lane); columns past q read column 0 (they reach only outputs that
+  // are never stored)
+  auto stage_y = [&](int sl, double *dst) {
+    // lane position pp (16 bytes) of the slab row holds columns 4 (pp % 16)
+    // + 2 (pp / 16) and the next one (the slab_pos layout)
+    const int pp = lane & 31;
+    const int c = sl * kTile + 4 * (pp & 15) + 2 * (pp >> 4);
+    const double *src = Y + (c < q ? c : 0);
+    for (int k0 = 2 * wave; k0 < p; k0 += 8) {
+      const int k = k0 + (lane >> 5);
+      __builtin_amdgcn_global_load_lds(
+          (const void *)(src + (int64_t)k * ldy),
+          (__attribute__((address_space(3))) void *)(dst + k0 * kTile), 16, 0, 0);
+    }
+  };
+  // Cin of slab sl straight into an accumulator set (the sums start from it)
+  auto load_cin = [&](int64_t rl, int sl, d4 (&acc)[4][2]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int col = sl * kTile + 4 * g + 16 * e + x;
+        const double2 t =
+            *reinterpret_cast<const double2 *>(Cin + (int64_t)(col < q ? col : 0) * ldci + rl);
+        acc[x][0][e] = t.x;
+        acc[x][1][e] = t.y;
+      }
+  };
+  double lv[kUpdMaxK / 16][4][2];  // L[rl + y][16 ks + 4 s + g]: this wave's rows of L
+  auto store = [&](int64_t rl, int sl, const d4 (&acc)[4][2]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int col = sl * kTile + 4 * g + 16 * e + x;
+        if (col < q)
+          *reinterpret_cast<double2 *>(C + (int64_t)col * ldc + rl) = double2{acc[x][0][e], acc[x][1][e]};
+      }
+  };
+
+  // Slab sl of C: acc holds its Cin on entry and its result on exit; Y is
+  // in `rd`. `other` holds the previous slab's result: it is stored first
+  // (stores issued a whole slab before the barrier that closes this one,
+  // which waits for every outstanding memory operation, have long
+  // completed) and then receives the next slab's Cin, while the next slab's
+  // Y is copied into `wr`. The last slab fetches itself again: unconditional
+  // loads keep the compiler from moving registers, which would make it wait
+  // for the loads right away.
+  auto slab = [&](int64_t rl, int sl, const double *rd, double *wr, d4 (&acc)[4][2],
+                  d4 (&other)[4][2]) {
+    if (sl > 0) store(rl, sl - 1, other);
+    const int nx = (sl + 1 < nslab) ? sl + 1 : sl;
+    stage_y(nx, wr);
+    load_cin(rl, nx, other);
+    __builtin_amdgcn_sched_barrier(0);
+    const double *yl = rd + 2 * cl;  // this lane's 4 columns (two halves)
+#pragma unroll
+    for (int ks = 0; ks < kUpdMaxK / 16; ++ks) {
+      if (ks < nk) {
+        // the k step's Y from LDS first, then its 32 MFMAs (only the first
+        // read's latency is exposed)
+        double ya[4][4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int k = 16 * ks + 4 * s + g;
+          const double2 y0 = *reinterpret_cast<const double2 *>(yl + k * kTile);
+          const double2 y1 = *reinterpret_cast<const double2 *>(yl + k * kTile + 32);
+          ya[s][0] = y0.x;
+          ya[s][1] = y0.y;
+          ya[s][2] = y1.x;
+          ya[s][3] = y1.y;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x4(ya[s][x], lv[ks][s][y], acc[x][y]);
+      }
+    }
+    if (sl == nslab - 1) store(rl, sl, acc);  // the row block's last slab
+    __syncthreads();  // this slab's buffer is free; the next slab's copy has landed
+  };
+
+  d4 acc0[4][2], acc1[4][2];
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t rl = blk * kLrRows + 32 * wave + 2 * cl;  // this lane's 2 rows
+#pragma unroll
+    for (int ks = 0; ks < kUpdMaxK / 16; ++ks)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if (ks < nk) {
+          const double2 t =
+              *reinterpret_cast<const double2 *>(L + (int64_t)(16 * ks + 4 * s + g) * ldl + rl);
+          lv[ks][s][0] = t.x;
+          lv[ks][s][1] = t.y;
+        } else {
+          lv[ks][s][0] = lv[ks][s][1] = 0.0;
+        }
+      }
+    stage_y(0, ys0);
+    load_cin(rl, 0, acc0);
+    __syncthreads();  // the first slab's copy has landed (the compiler waits for it)
+    for (int sl = 0; sl < nslab; sl += 2) {
+      slab(rl, sl, ys0, ys1, acc0, acc1);
+      if (sl + 1 < nslab) slab(rl, sl + 1, ys1, ys0, acc1, acc0);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// k_nn_wide: the update C = Cin + L Y (Y = -projection, row-major p x q) with
+// one wave per 64-row x 16NX-column tile of C and the accumulators (4 x NX
+// MFMA blocks: 128 doubles at NX = 8) held across the whole inner dimension.
+// Each 16-wide k step loads 16 L values and 4 NX Y values per lane for 16 NX
+// MFMAs (128 at NX = 8), against 8 + 16 values for 32 MFMAs in k_nn's 32 x 64
+// tiles, so the operand traffic per MFMA is about a third; Y (the short,
+// L2-resident side) is read from global memory directly. Lane/element maps
+// (cl = lane % 16, g = lane / 16, y < 4 row blocks, x < NX column blocks):
+//   B operand, block y: lane holds L[r0 + 4 cl + y][k],  k = kk + 4 s + g
+//   A operand, block x: lane holds Y[k][c0 + NX cl + x]
+//   D element e of block (x, y): C[r0 + 4 cl + y][c0 + NX (g + 4 e) + x]
+// so a lane's L and C accesses are 4 consecutive doubles of one column and
+// its Y accesses NX consecutive doubles of one row. Every element is summed
+// in the order of k_nn and k_upd (Cin first, then k steps ascending with the
+// same groups of four per MFMA), so the three kernels agree bit for bit.
+// Fast path: the tile's rows all exist, p is a multiple of 16 and each
+// lane's NX columns are all < q or all >= q (those lanes read column 0: their
+// outputs are never stored); anything else takes the masked loop.
+// SUB = false, TRI = true: the in-place product Q = X U^{-1} (Y = U^{-1}
+// upper triangular, L = C = X, no Cin): a workgroup holds one wave per
+// 128-column tile of one 64-row tile, every wave sums k < c0 + 128 only (the
+// rest of U^{-1}'s column is zero) from zero, and a workgroup barrier
+// separates the last read of the rows from the first write. k_trsm and
+// k_nn<TRI> sum the same terms in the same order (their extra k steps only
+// add exact zeros), so all three agree bit for bit. C2 (optional) receives
+// the same values as C.
+// ----------------------------------------------------------------------------
+template <int NX, bool SUB, bool TRI>
+__global__ __launch_bounds__(128) void k_nn_wide(int64_t m, int p, int q, const double *L,
+                                                 int64_t ldl, const double *__restrict__ Y,
+                                                 int64_t ldy, const double *Cin, int64_t ldci,
+                                                 double *C, int64_t ldc, int nct, double *C2,
+                                                 int64_t ldc2, const int *__restrict__ info,
+                                                 const int *__restrict__ skip) {
+  if (*info || (skip && *skip)) return;
+  constexpr int kCols = 16 * NX;
+  const int nw = blockDim.x >> 6;  // waves (column tiles) per workgroup
+  const int64_t lid = xcd_logical(blockIdx.x, gridDim.x);
+  const int groups = nct / nw;  // workgroups per row tile
+  const int64_t r0 = (lid / groups) * 64;
+  const int c0 = ((int)(lid % groups) * nw + (int)(threadIdx.x >> 6)) * kCols;
+  const int kend = TRI ? ((c0 + kCols < p) ? c0 + kCols : p) : p;
+  const int lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const int64_t rl = r0 + 4 * cl;  // this lane's 4 rows
+  const int yc = c0 + NX * cl;     // this lane's NX columns of Y
+
+  // FAST: every row of the tile exists, p % 16 == 0 and each lane's NX
+  // columns are all < q or all >= q. The two forms are separate code paths
+  // so that the accumulators never merge across them.
+  auto body = [&](auto fast_c) {
+    constexpr bool FAST = decltype(fast_c)::value;
+    d4 acc[NX][4];  // [column block x][row block y]
+    // Cin into the accumulators, each one whole (its four columns, one row)
+    // before the next is started, one column block per scheduling region:
+    // building them element by element made the compiler hold all of them
+    // in VGPRs at once and spill
+#pragma unroll
+    for (int x = 0; x < NX; ++x) {
+      if (!SUB) {
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+        continue;
+      }
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        d4 v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int col = c0 + NX * (g + 4 * e) + x;
+          const double *pc = Cin + (int64_t)(col < q ? col : 0) * ldci + rl + y;
+          v[e] = (FAST || (col < q && rl + y < m)) ? *pc : 0.0;
+        }
+        acc[x][y] = mfma16x16x4(0.0, 0.0, v);  // = v, placed as an accumulator
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    auto compute = [&](const double (&da)[4][NX], const double (&db)[4][4]) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int x = 0; x < NX; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x4(da[s][x], db[s][y], acc[x][y]);
+    };
+    if (FAST) {
+      const double *yb = Y + (yc < q ? yc : 0) + (int64_t)g * ldy;
+      const double *lb = L + (int64_t)g * ldl + rl;
+      auto load = [&](double (&da)[4][NX], double (&db)[4][4], int kk) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double2 *py = reinterpret_cast<const double2 *>(yb + (int64_t)(kk + 4 * s) * ldy);
+#pragma unroll
+          for (int h = 0; h < NX / 2; ++h) {
+            const double2 t = py[h];
+            da[s][2 * h] = t.x;
+            da[s][2 * h + 1] = t.y;
+          }
+          const double2 *pl = reinterpret_cast<const double2 *>(lb + (int64_t)(kk + 4 * s) * ldl);
+          const double2 l0 = pl[0], l1 = pl[1];
+          db[s][0] = l0.x;
+          db[s][1] = l0.y;
+          db[s][2] = l1.x;
+          db[s][3] = l1.y;
+        }
+      };
+      // two register stages: while one step's MFMAs run, the next step's
+      // loads are in flight (16 NX MFMAs of cover)
+      const int nit = kend / 16;
+      double a0[4][NX], b0[4][4], a1[4][NX], b1[4][4];
+      auto at = [&](int st) -> int { return 16 * (st < nit ? st : nit - 1); };
+      if (nit > 0) {
+        load(a0, b0, 0);
+        int it = 0;
+        for (; it + 2 <= nit; it += 2) {
+          load(a1, b1, at(it + 1));
+          __builtin_amdgcn_sched_barrier(0);
+          compute(a0, b0);
+          __builtin_amdgcn_sched_barrier(0);
+          load(a0, b0, at(it + 2));
+          __builtin_amdgcn_sched_barrier(0);
+          compute(a1, b1);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (it < nit) compute(a0, b0);
+      }
+    } else {
+      for (int kk = 0; kk < kend; kk += 16) {
+        double da[4][NX], db[4][4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int k = kk + 4 * s + g;
+          const bool kok = k < kend;
+          const double *py = Y + (int64_t)(kok ? k : 0) * ldy;
+          const double *pl = L + (int64_t)(kok ? k : 0) * ldl;
+#pragma unroll
+          for (int x = 0; x < NX; ++x) da[s][x] = (kok && yc + x < q) ? py[yc + x] : 0.0;
+#pragma unroll
+          for (int y = 0; y < 4; ++y) db[s][y] = (kok && rl + y < m) ? pl[rl + y] : 0.0;
+        }
+        compute(da, db);
+      }
+    }
+    if (!SUB) __syncthreads();  // in place: every read of the rows precedes every write
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int x = 0; x < NX; ++x) {
+        const int col = c0 + NX * (g + 4 * e) + x;
+        if (col < q) {
+          double *pc = C + (int64_t)col * ldc + rl;
+          double *pc2 = C2 ? C2 + (int64_t)col * ldc2 + rl : nullptr;
+          if (FAST) {
+            const double2 v0 = double2{acc[x][0][e], acc[x][1][e]};
+            const double2 v1 = double2{acc[x][2][e], acc[x][3][e]};
+            reinterpret_cast<double2 *>(pc)[0] = v0;
+            reinterpret_cast<double2 *>(pc)[1] = v1;
+            if (pc2) {
+              reinterpret_cast<double2 *>(pc2)[0] = v0;
+              reinterpret_cast<double2 *>(pc2)[1] = v1;
+            }
+          } else {
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+              if (rl + y < m) {
+                pc[y] = acc[x][y][e];
+                if (pc2) pc2[y] = acc[x][y][e];
+              }
+          }
+        }
+      }
+  };
+  if ((r0 + 64 <= m) && (kend % 16 == 0) && ((q % NX) == 0 || c0 + kCols <= q))
+    body(std::true_type{});
+  else
+    body(std::false_type{});
 }
 
 // ----------------------------------------------------------------------------
@@ -952,11 +1284,11 @@ __global__ __launch_bounds__(512, 1) void k_nn_ys(int64_t m, int p, int q, const
   const int64_t re = (rb + rows_per_wg < m) ? rb + rows_per_wg : m;
   for (int e = threadIdx.x; e < p * kTile; e += 512) {
     const int k = e / kTile, c = c0 + e % kTile;
-    ys[e] = (c < q) ? Y[(int64_t)k * ldy + c] : 0.0;
+    ys[k * kTile + slab_pos(e % kTile)] = (c < q) ? Y[(int64_t)k * ldy + c] : 0.0;
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
-  const double *yl = ys + 4 * cl;
+  const double *yl = ys + 2 * cl;  // this lane's 4 columns (two halves, slab_pos layout)
   const int nit = p / 16;
   for (int64_t r0 = rb + 32 * wave; r0 < re; r0 += 256) {
     const int64_t rl = r0 + 2 * cl;
@@ -991,7 +1323,7 @@ __global__ __launch_bounds__(512, 1) void k_nn_ys(int64_t m, int p, int q, const
       for (int s = 0; s < 4; ++s) {
         const int k = kk + 4 * s + g;
         const double2 y0 = *reinterpret_cast<const double2 *>(yl + k * kTile);
-        const double2 y1 = *reinterpret_cast<const double2 *>(yl + k * kTile + 2);
+        const double2 y1 = *reinterpret_cast<const double2 *>(yl + k * kTile + 32);
         ya[s][0] = y0.x;
         ya[s][1] = y0.y;
         ya[s][2] = y1.x;
@@ -1056,11 +1388,28 @@ static int device_cus() {
   return cus > 0 ? cus : 256;
 }
 
+// The single-matrix update's kernel: the requested variant where it applies,
+// else the default: the LDS-slab kernel for inner dimensions up to kUpdMaxK
+// (measured at 2^22 rows, 128 inner x 896 columns: 9.5 ms against 11.6 ms
+// for the wide tiles, whose C traffic per MFMA is the same but whose whole
+// tile of Cin loads is exposed at the start of each short tile), the 64 x 128
+// register tiles for longer ones (896 inner x 128 columns: 9.7 ms against
+// 10.8 ms for the 32 x 64 tiles), the 32 x 64 tiles where neither applies.
+int update_variant(int tile, bool res_ok, bool slab_ok, bool wide_ok) {
+  if (!wide_ok && !slab_ok) return kTileNarrow;
+  if (tile == kTileWide && wide_ok) return kTileWide;
+  if (tile == kTileNarrow) return kTileNarrow;
+  if (tile == kTileSlab && slab_ok) return kTileSlab;
+  if (tile == kTileResident && res_ok) return kTileResident;
+  return slab_ok ? kTileSlab : (wide_ok ? kTileWide : kTileNarrow);
+}
+
 hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const double *L,
                      int64_t ldl, const double *Y, int64_t ldy, const double *Cin, int64_t ldci,
                      double *C, int64_t ldc, const int *info, hipStream_t s, const double *L2,
                      int64_t ldl2, int psplit, int batch, int64_t sL, int64_t sL2, int64_t sY,
-                     int64_t sCin, int64_t sC, double *C2, int64_t ldc2, const int *skip) {
+                     int64_t sCin, int64_t sC, double *C2, int64_t ldc2, const int *skip,
+                     int tile) {
   if (C2 && (subtract || batch != 1)) return hipErrorInvalidValue;
   if (!L2) {
     L2 = L;
@@ -1100,6 +1449,24 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
                        ldy, C, ldc, slabs, rpw, sL, sL2, sY, sC, info);
     return hipGetLastError();
   }
+  // Q = X U^{-1} for a panel width k_trsm does not take (wider than 128, or
+  // ragged): one wave per 64 x 128 (64 x 64 up to 64 columns) tile, the
+  // tiles of one row tile in one workgroup (reads before writes)
+  if (!subtract && upper_y && batch == 1 && p == q && q <= 2 * kUpdMaxK && L2 == L &&
+      !(q == 64 || q == 128) && (ldl % 2 == 0) && (ldc % 2 == 0) && (ldy % 2 == 0) &&
+      ((uintptr_t)L % 16 == 0) && ((uintptr_t)C % 16 == 0) && ((uintptr_t)Y % 16 == 0) &&
+      (C2 == nullptr || ((ldc2 % 2 == 0) && ((uintptr_t)C2 % 16 == 0)))) {
+    const int nx = (q > 64) ? 8 : 4;
+    const int nct = (q + 16 * nx - 1) / (16 * nx);  // 1 or 2 waves per workgroup
+    const int64_t rts = (m + 63) / 64;
+    if (nx == 8)
+      hipLaunchKernelGGL((k_nn_wide<8, false, true>), dim3((unsigned)rts), dim3(64 * nct), 0, s, m,
+                         p, q, L, ldl, Y, ldy, nullptr, 0, C, ldc, nct, C2, ldc2, info, skip);
+    else
+      hipLaunchKernelGGL((k_nn_wide<4, false, true>), dim3((unsigned)rts), dim3(64 * nct), 0, s, m,
+                         p, q, L, ldl, Y, ldy, nullptr, 0, C, ldc, nct, C2, ldc2, info, skip);
+    return hipGetLastError();
+  }
   if (!subtract && ncg != 1) return hipErrorInvalidValue;  // in-place needs one column group
   if (!subtract && upper_y && batch == 1 && p == q && (q == 64 || q == 128) &&
       m >= kTrsmRows && Cin == C && (L == C || ldl >= m) && ldy == q && L2 == L) {
@@ -1136,7 +1503,43 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
                      ldc, info, s, nullptr, 0, 0, 1, 0, 0, 0, 0, 0, C2 ? C2 + mfull : nullptr, ldc2,
                      skip);
   }
-  if (subtract && batch == 1 && psplit == p && nn_short_k(p, L, ldl, Cin, ldci, C, ldc)) {
+  // single-matrix update: the kernel variant is a tuning choice (tile)
+  const bool one_update = subtract && batch == 1 && psplit == p && C2 == nullptr;
+  const bool wide_ok = one_update && (ldl % 2 == 0) && (ldci % 2 == 0) && (ldc % 2 == 0) &&
+                       (ldy % 2 == 0) && ((uintptr_t)L % 16 == 0) && ((uintptr_t)Cin % 16 == 0) &&
+                       ((uintptr_t)C % 16 == 0) && ((uintptr_t)Y % 16 == 0);
+  const bool slab_ok = one_update && nn_short_k(p, L, ldl, Cin, ldci, C, ldc);
+  const bool res_ok = slab_ok && p % 16 == 0 && m >= kLrRows && (ldy % 2 == 0) &&
+                      ((uintptr_t)Y % 16 == 0);
+  const int upd = update_variant(tile, res_ok, slab_ok, wide_ok);
+  if (upd == kTileWide) {
+    const int nx = (q > 64) ? 8 : 4;
+    const int nct = (q + 16 * nx - 1) / (16 * nx);
+    const int64_t rts = (m + 63) / 64;
+    const dim3 gw((unsigned)(rts * nct));
+    if (nx == 8)
+      hipLaunchKernelGGL((k_nn_wide<8, true, false>), gw, dim3(64), 0, s, m, p, q, L, ldl, Y, ldy,
+                         Cin, ldci, C, ldc, nct, nullptr, 0, info, skip);
+    else
+      hipLaunchKernelGGL((k_nn_wide<4, true, false>), gw, dim3(64), 0, s, m, p, q, L, ldl, Y, ldy,
+                         Cin, ldci, C, ldc, nct, nullptr, 0, info, skip);
+    return hipGetLastError();
+  }
+  if (upd == kTileResident) {
+    // rows in whole 128-row blocks: one persistent workgroup per CU (its LDS
+    // holds the two Y slabs); the remaining rows by the slab kernel below
+    static const int cus = device_cus();
+    const int64_t mfull = m / kLrRows * kLrRows;
+    const int64_t grid = std::min<int64_t>(mfull / kLrRows, std::max(cus, 1));
+    hipLaunchKernelGGL(k_upd_lr, dim3((unsigned)grid), dim3(256), 0, s, mfull, p, q, L, ldl, Y, ldy,
+                       Cin, ldci, C, ldc, info, skip);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess || mfull == m) return e;
+    return launch_nn(true, false, m - mfull, p, q, L + mfull, ldl, Y, ldy, Cin + mfull, ldci,
+                     C + mfull, ldc, info, s, nullptr, 0, 0, 1, 0, 0, 0, 0, 0, nullptr, 0, skip,
+                     kTileSlab);
+  }
+  if (upd == kTileSlab) {
     // one round of resident workgroups (two per CU): each slab gets an equal
     // share of them, each with an equal range of rows (a multiple of 32)
     static const hipError_t attr = hipFuncSetAttribute(

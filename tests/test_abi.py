@@ -169,3 +169,17 @@ def test_noalloc_argument_errors(lib):
     assert _lib.workspace_bytes(m, n, b, 0) <= _lib.CQR_NOALLOC_SCRATCH_BYTES
     text = open(os.path.join(ROOT, "include", "cqr.h")).read()
     assert re.search(r"#define CQR_NOALLOC_SCRATCH_BYTES \(\(size_t\)128 << 20\)", text)
+
+
+@pytest.mark.parametrize("ut,pt", [(-1, 0), (5, 0), (0, -1), (0, 5)])
+def test_tile_option_errors(lib, ut, pt):
+    """Kernel-variant options outside enum cqr_tile are argument errors."""
+    st = _lib.factor_ex(100, 10, 4, FAKE, 100, FAKE, FAKE, None, 0, None, None, 0,
+                        update_tile=ut, proj_tile=pt)
+    assert st == _lib.CQR_ERR_ARG
+
+
+def test_tile_constants_match_header():
+    text = open(os.path.join(ROOT, "include", "cqr.h")).read()
+    for name, val in _lib.TILES.items():
+        assert re.search(rf"CQR_TILE_{name.upper()} = {val}\b", text), name

@@ -686,6 +686,7 @@ __global__ __launch_bounds__(256, (RB == 2) ? 2 : 1) void k_nn(
 // XCD's L2) and differ in the slab.
 // ----------------------------------------------------------------------------
 constexpr int kUpdMaxK = 128;
+constexpr int kLdsPanelRows = 128;  // U^{-1} block k_trsm holds in LDS
 
 // Position in a 64-column LDS slab row of column j (0..63): each lane of the
 // update kernels reads its 4 consecutive columns 4 cl .. 4 cl + 3 as two
@@ -1449,13 +1450,31 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
                        ldy, C, ldc, slabs, rpw, sL, sL2, sY, sC, info);
     return hipGetLastError();
   }
-  // Q = X U^{-1} for a panel width k_trsm does not take (wider than 128, or
-  // ragged): one wave per 64 x 128 (64 x 64 up to 64 columns) tile, the
-  // tiles of one row tile in one workgroup (reads before writes)
-  if (!subtract && upper_y && batch == 1 && p == q && q <= 2 * kUpdMaxK && L2 == L &&
-      !(q == 64 || q == 128) && (ldl % 2 == 0) && (ldc % 2 == 0) && (ldy % 2 == 0) &&
-      ((uintptr_t)L % 16 == 0) && ((uintptr_t)C % 16 == 0) && ((uintptr_t)Y % 16 == 0) &&
-      (C2 == nullptr || ((ldc2 % 2 == 0) && ((uintptr_t)C2 % 16 == 0)))) {
+  const bool tri_wide_ok = !subtract && upper_y && batch == 1 && p == q && L2 == L &&
+                           (ldl % 2 == 0) && (ldc % 2 == 0) && (ldy % 2 == 0) &&
+                           ((uintptr_t)L % 16 == 0) && ((uintptr_t)C % 16 == 0) &&
+                           ((uintptr_t)Y % 16 == 0) &&
+                           (C2 == nullptr || ((ldc2 % 2 == 0) && ((uintptr_t)C2 % 16 == 0)));
+  // Q = X U^{-1} for 256 columns: the right half [X_l X_r] [B; C] first (in
+  // place: it reads the left half, which is still X), then the left half
+  // X_l A by the persistent kernel with A's 128 x 128 block in LDS. Same
+  // bits as one triangular product (the right half's extra k terms are the
+  // zero entries below U^{-1}'s diagonal).
+  if (tri_wide_ok && q == 2 * kLdsPanelRows && (L == C || ldl >= m) && Cin == C && m >= 128) {
+    const int h = kLdsPanelRows;
+    const int64_t rts = (m + 63) / 64;
+    hipLaunchKernelGGL((k_nn_wide<8, false, false>), dim3((unsigned)rts), dim3(64), 0, s, m, p, h,
+                       L, ldl, Y + h, ldy, nullptr, 0, C + (int64_t)h * ldc, ldc, 1,
+                       C2 ? C2 + (int64_t)h * ldc2 : nullptr, ldc2, info, skip);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_nn(false, true, m, h, h, L, ldl, Y, ldy, nullptr, 0, C, ldc, info, s, nullptr, 0,
+                     0, 1, 0, 0, 0, 0, 0, C2, ldc2, skip);
+  }
+  // Q = X U^{-1} for another panel width k_trsm does not take (ragged, or
+  // between 128 and 256): one wave per 64 x 128 (64 x 64 up to 64 columns)
+  // tile, the tiles of one row tile in one workgroup (reads before writes)
+  if (tri_wide_ok && q <= 2 * kUpdMaxK && !(q == 64 || q == 128)) {
     const int nx = (q > 64) ? 8 : 4;
     const int nct = (q + 16 * nx - 1) / (16 * nx);  // 1 or 2 waves per workgroup
     const int64_t rts = (m + 63) / 64;
@@ -1469,7 +1488,7 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
   }
   if (!subtract && ncg != 1) return hipErrorInvalidValue;  // in-place needs one column group
   if (!subtract && upper_y && batch == 1 && p == q && (q == 64 || q == 128) &&
-      m >= kTrsmRows && Cin == C && (L == C || ldl >= m) && ldy == q && L2 == L) {
+      m >= kTrsmRows && Cin == C && (L == C || ldl >= m) && ldy >= q && L2 == L) {
     // Q = X U^{-1} (in place or from a separate X): persistent
     // U^{-1}-in-LDS kernel over the full row blocks, k_nn for the remaining
     // rows

@@ -71,11 +71,15 @@ template <int NA, int NB>
 __device__ __forceinline__ void tn_run(int64_t m, int na, int nb, const double *A, int64_t lda,
                                        const double *B, int64_t ldb, bool vec, double *out, int ldo,
                                        bool trans) {
-  constexpr int U = (NA + NB <= 2) ? 4 : ((NA + NB) * 2 <= 10 ? 2 : 1);  // 16-row steps per stage
+  // 16-row steps per ring stage: a stage holds at most 24 doubles per lane,
+  // so that the whole kernel fits two workgroups per compute unit
+  constexpr int U = (NA + NB <= 3) ? 2 : 1;
   constexpr int SR = 16 * U;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, cl = lane & 15;
-  const int rows_out = trans ? nb : na;
-  for (int e = tid; e < rows_out * ldo; e += kThreads) out[e] = 0.0;
+  for (int e = tid; e < na * nb; e += kThreads) {
+    const int i = e / nb, j = e % nb;
+    out[trans ? j * ldo + i : i * ldo + j] = 0.0;
+  }
   __syncthreads();
 
   // columns past na / nb read column 0: they reach only outputs never stored
@@ -160,22 +164,7 @@ __device__ __forceinline__ void tn_run(int64_t m, int na, int nb, const double *
       compute(v);
       if ((r + 1) % per_flush == 0) flush();
     };
-    if constexpr (NA + NB > 6) {  // wide products: two stages (64 MFMAs of cover each)
-      Stage v0, v1;
-      load(v0, 0);
-      int64_t r = 0;
-      for (; r + 2 <= nfull; r += 2) {
-        load(v1, at(r + 1));
-        __builtin_amdgcn_sched_barrier(0);
-        step(v0, r);
-        __builtin_amdgcn_sched_barrier(0);
-        load(v0, at(r + 2));
-        __builtin_amdgcn_sched_barrier(0);
-        step(v1, r + 1);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      if (r < nfull) step(v0, r);
-    } else {
+    {
       Stage v0, v1, v2;
       load(v0, 0);
       load(v1, at(1));
@@ -220,22 +209,25 @@ __device__ __forceinline__ void tn_run(int64_t m, int na, int nb, const double *
 }
 
 // One call site for every TN product of the factorisation: dispatch on the
-// block counts (A side <= 2 blocks: the panel; B side <= 8: up to 128 columns).
+// block counts (A side <= 2 blocks: the panel; B side up to 8 blocks, 128
+// columns, taken in passes of at most 4 blocks: wider passes need more
+// accumulators than two workgroups per compute unit leave a wave).
 __device__ __forceinline__ void wg_tn(int64_t m, int na, int nb, const double *A, int64_t lda,
                                    const double *B, int64_t ldb, double *out, int ldo, bool trans) {
   const bool vec = (lda % 2 == 0) && (ldb % 2 == 0) && ((uintptr_t)A % 16 == 0) &&
                    ((uintptr_t)B % 16 == 0);
-  const int ka = (na + 15) / 16, kb = (nb + 15) / 16;
-#define CQR_TN_CASE(X, Y)                                             \
-  if (ka == X && kb == Y) {                                           \
-    tn_run<X, Y>(m, na, nb, A, lda, B, ldb, vec, out, ldo, trans);    \
-    return;                                                           \
-  }
-  CQR_TN_CASE(1, 1) CQR_TN_CASE(1, 2) CQR_TN_CASE(1, 3) CQR_TN_CASE(1, 4)
-  CQR_TN_CASE(1, 5) CQR_TN_CASE(1, 6) CQR_TN_CASE(1, 7) CQR_TN_CASE(1, 8)
-  CQR_TN_CASE(2, 1) CQR_TN_CASE(2, 2) CQR_TN_CASE(2, 3) CQR_TN_CASE(2, 4)
-  CQR_TN_CASE(2, 5) CQR_TN_CASE(2, 6) CQR_TN_CASE(2, 7) CQR_TN_CASE(2, 8)
+  const int ka = (na + 15) / 16;
+  for (int j0 = 0; j0 < nb; j0 += 64) {
+    const int nbp = (nb - j0 < 64) ? nb - j0 : 64;
+    const int kb = (nbp + 15) / 16;
+    const double *Bp = B + (int64_t)j0 * ldb;
+    double *op = out + (trans ? (int64_t)j0 * ldo : j0);
+#define CQR_TN_CASE(X, Y)                                               \
+    if (ka == X && kb == Y) tn_run<X, Y>(m, na, nbp, A, lda, Bp, ldb, vec, op, ldo, trans);
+    CQR_TN_CASE(1, 1) CQR_TN_CASE(1, 2) CQR_TN_CASE(1, 3) CQR_TN_CASE(1, 4)
+    CQR_TN_CASE(2, 1) CQR_TN_CASE(2, 2) CQR_TN_CASE(2, 3) CQR_TN_CASE(2, 4)
 #undef CQR_TN_CASE
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -264,10 +256,10 @@ __device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, 
   const int64_t T = mine * nk;                                            // steps
 
   struct Stage {
-    double l[4][2];     // L[rl + y][k], k = 16 ks + 4 s + g
-    double c[4][4][2];  // Cin[rl + y][c0 + 4 g + 16 e + x] (a tile's first step)
+    double l[4][2];  // L[rl + y][k], k = 16 ks + 4 s + g
   };
   d4 acc[4][2];
+  double cn[4][4][2];  // Cin[rl + y][c0 + 4 g + 16 e + x] of the next tile to start
 
   auto tile_of = [&](int64_t i, int64_t &r0, int &c0) {  // i-th tile of this wave
     const int64_t t = wave + 4 * i;
@@ -359,7 +351,8 @@ __device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, 
   };
 
   if (T > 0) {
-    // load cursor
+    // load cursor (L only: a tile's Cin is loaded when the tile before it
+    // starts, into cn, so the ring stages stay small)
     int64_t li = 0, lr0;
     int lc0, lks = 0;
     tile_of(0, lr0, lc0);
@@ -367,7 +360,6 @@ __device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, 
     auto load = [&](Stage &st) {
       const int64_t rl = lr0 + 2 * cl;
       load_l(st.l, rl, lks, 2);
-      if (lks == 0) load_c(st.c, rl, lc0, 2);
       if (lt + 1 < T) {  // advance (past the end the last step is loaded again)
         ++lt;
         if (++lks == nk) {
@@ -380,8 +372,17 @@ __device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, 
     int64_t ci = 0, cr0;
     int cc0, cks = 0;
     tile_of(0, cr0, cc0);
+    load_c(cn, cr0 + 2 * cl, cc0, 2);
     auto step = [&](const Stage &st) {
-      if (cks == 0) init_acc(st.c);
+      if (cks == 0) {
+        init_acc(cn);
+        // the next tile's Cin (the last tile loads its own again: an
+        // unconditional load keeps the registers in place)
+        int64_t nr0;
+        int nc0;
+        tile_of(ci + 1 < mine ? ci + 1 : ci, nr0, nc0);
+        load_c(cn, nr0 + 2 * cl, nc0, 2);
+      }
       mma(st.l, cks, cc0);
       if (++cks == nk) {
         store(cr0 + 2 * cl, cc0, 2);
@@ -419,8 +420,8 @@ __device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, 
       const int64_t rl = r0 + 2 * cl;
       const int64_t left = m - rl;
       Stage st;
-      load_c(st.c, rl, c0, left);
-      init_acc(st.c);
+      load_c(cn, rl, c0, left);
+      init_acc(cn);
       for (int ks = 0; ks < nk; ++ks) {
         load_l(st.l, rl, ks, left);
         mma(st.l, ks, c0);

@@ -522,14 +522,19 @@ int check_args(int64_t m, int64_t n, int64_t b, const double *A, int64_t lda, co
 
 // ---------------------------------------------------------------- backward
 struct BwdLayout {
-  int64_t info, part, t, rinv, c, g, y, gw, total;
+  int64_t info, part, t, rinv, rinvt, c, g, y, total;
   int64_t nch, rc, ldy;
 };
 
 BwdLayout make_bwd_layout(int64_t m, int64_t n, int64_t batch) {
   BwdLayout L{};
+  // pass 1 (upper 64 x 64 tiles): about one round of resident waves
+  // (kWaveSlots), so that every wave streams a long run of rows; the
+  // factorisation's plan (two rounds or more) cut 262144 rows into 400-row
+  // chunks whose partials and start-up cost as much as their products
   const int64_t tiles = cqr::tn_tiles(true, (int)n, (int)n);
-  int64_t want = split_m_chunks(m, tiles * batch);
+  int64_t want = std::max<int64_t>(1, kWaveSlots / (tiles * batch));
+  want = std::max(want, (m + kMaxChunkRows - 1) / kMaxChunkRows);
   want = std::min({want, (m + 15) / 16, int64_t(1024)});
   want = std::max<int64_t>(want, 1);
   L.rc = round_up((m + want - 1) / want, 16);
@@ -545,10 +550,10 @@ BwdLayout make_bwd_layout(int64_t m, int64_t n, int64_t batch) {
   L.part = take(8 * batch * L.nch * n * n);
   L.t = take(8 * batch * n * n);
   L.rinv = take(8 * batch * n * n);
+  L.rinvt = take(8 * batch * n * n);
   L.c = take(8 * batch * n * n);
   L.g = take(8 * batch * n * n);
   L.y = take(8 * batch * 2 * n * L.ldy);
-  L.gw = take(8 * batch * cqr::chol_scratch_doubles((int)n));  // R^{-1} of n > kLdsPanel
   L.total = off;
   return L;
 }
@@ -863,8 +868,9 @@ int cqr_backward_batched(int64_t batch, int64_t m, int64_t n, const double *Q, c
   }
   int *info = (int *)(ws + lay.info);
   double *part = (double *)(ws + lay.part), *T = (double *)(ws + lay.t);
-  double *Rinv = (double *)(ws + lay.rinv), *C = (double *)(ws + lay.c), *G = (double *)(ws + lay.g);
-  double *Y = (double *)(ws + lay.y), *Gw = (double *)(ws + lay.gw);
+  double *Rinv = (double *)(ws + lay.rinv), *RinvT = (double *)(ws + lay.rinvt);
+  double *C = (double *)(ws + lay.c), *G = (double *)(ws + lay.g);
+  double *Y = (double *)(ws + lay.y);
   const int ni = (int)n, b = (int)batch;
   const int64_t nn = n * n, sy = 2 * n * lay.ldy;
   const bool recompute = (Q == nullptr);
@@ -883,8 +889,9 @@ int cqr_backward_batched(int64_t batch, int64_t m, int64_t n, const double *Q, c
                       [&] { return cqr::launch_zero2d(dA, m, n, lda, stride, b, s); }));
   hipError_t e = cqr::launch_set_int(info, 0, s);
   if (e != hipSuccess) return CQR_ERR_HIP;
-  // R^{-1} needs only R: it runs on the side stream while pass 1 streams
-  // over the rows, and is joined back before the n x n step
+  // R^{-1} and R^{-T} need only R: they run on the side stream while pass 1
+  // streams over the rows, and are joined back before the n x n step (the
+  // inverse's waves use few registers, so they share SIMDs with pass 1's)
   DevState *dev_state = nullptr;
   if (side_stream(&dev_state) != hipSuccess) return CQR_ERR_HIP;
   std::lock_guard<std::mutex> side_lock(dev_state->side);
@@ -893,7 +900,7 @@ int cqr_backward_batched(int64_t batch, int64_t m, int64_t n, const double *Q, c
       hipStreamWaitEvent(aux, dev_state->fork, 0) != hipSuccess)
     return CQR_ERR_HIP;
   e = timed(aux, CQR_K_CHOL, bf * nf * nf * nf / 3.0, 16.0 * bf * nn,
-            [&] { return cqr::launch_tri_inv(R, ni, nn, Rinv, nn, b, aux, Gw); });
+            [&] { return cqr::launch_tri_inv(R, ni, nn, Rinv, nn, b, aux, RinvT); });
   if (e != hipSuccess) return CQR_ERR_HIP;
   if (hipEventRecord(dev_state->join, aux) != hipSuccess) return CQR_ERR_HIP;
   // pass 1: T = S^T dQ (upper 64x64 tiles), split over m, fixed-order reduce
@@ -913,7 +920,7 @@ int cqr_backward_batched(int64_t batch, int64_t m, int64_t n, const double *Q, c
   // n x n part: C = copyltu(M), the stacked right operand (after R^{-1})
   if (hipStreamWaitEvent(s, dev_state->join, 0) != hipSuccess) return CQR_ERR_HIP;
   e = timed(s, CQR_K_SMALL, bf * 2.0 * nf * nf * nf, 8.0 * bf * 6 * nn, [&] {
-    return cqr::launch_adj_small(ni, T, nn, R, dR, nn, Rinv, nn, dQ ? 1 : 0, recompute ? 1 : 0, C, G,
+    return cqr::launch_adj_small(ni, T, nn, R, dR, nn, Rinv, RinvT, nn, dQ ? 1 : 0, recompute ? 1 : 0, C, G,
                                  nn, Y, lay.ldy, sy, dQ ? 1 : 0, b, s);
   });
   if (e != hipSuccess) return CQR_ERR_HIP;

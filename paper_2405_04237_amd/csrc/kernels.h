@@ -43,8 +43,10 @@ hipError_t launch_tn(bool gram, int64_t m, int p, int q, const double *L, int64_
                      int64_t sRt = 0, int64_t sPart = 0, int tile = kTileAuto);
 
 // Number of waves one row chunk of launch_tn occupies (its output tiles).
-// same: both operands are one matrix (a Gram matrix); with p = q = 128 that
-// selects the two-wave balanced Gram kernel. tile: as for launch_tn.
+// An upper product with p = q = 128 (batch 1) runs the two-wave balanced
+// kernel (one operand loaded once when both are the same matrix); `same` is
+// kept for callers and does not change the count. tile = kTileNarrow: the
+// count of the plain 64 x 64 tiles.
 int64_t tn_tiles(bool gram, int p, int q, bool same = false, int tile = kTileAuto);
 
 // Row-streaming product over all m rows, Y row-major p x q (leading dim ldy):
@@ -112,12 +114,13 @@ hipError_t launch_zskip(double *Z, int rows, int cols, int64_t ldz, double tol, 
                         const int *info, hipStream_t s);
 
 // Rinv = R^{-1} for `batch` upper triangular n x n matrices (R column-major
-// ld n at R + i*sR; Rinv row-major ld n at Rinv + i*sRi); n <= kMaxPanel;
-// for n > kLdsPanel, gwork holds batch * chol_scratch_doubles(n) doubles.
+// ld n at R + i*sR; Rinv row-major ld n at Rinv + i*sRi); n <= kMaxPanel.
+// RinvT (optional, same strides): R^{-T} row-major as well.
 hipError_t launch_tri_inv(const double *R, int n, int64_t sR, double *Rinv, int64_t sRi, int batch,
-                          hipStream_t s, double *gwork = nullptr);
+                          hipStream_t s, double *RinvT = nullptr);
 
-// The n x n part of the QR adjoint, per matrix i of the batch:
+// The n x n part of the QR adjoint, per matrix i of the batch (Rinv and
+// RinvT = R^{-1} and R^{-T}, both row-major, from launch_tri_inv):
 //   C = copyltu(R dR^T - P) with P = dQ^T Q taken from T = S^T dQ (upper
 //   triangle of a row-major n x n; S = Q, or A when recompute != 0, in which
 //   case Q = A R^{-1} is applied through Rinv); has_p = 0 drops P, dR =
@@ -127,9 +130,9 @@ hipError_t launch_tri_inv(const double *R, int n, int64_t sR, double *Rinv, int6
 //   R^{-1} G under recompute.
 // C and G are n x n row-major scratch at C + i*sCG, G + i*sCG.
 hipError_t launch_adj_small(int n, const double *T, int64_t sT, const double *R, const double *dR,
-                            int64_t sRn, const double *Rinv, int64_t sRi, int has_p, int recompute,
-                            double *C, double *G, int64_t sCG, double *Y, int64_t ldy, int64_t sY,
-                            int with_rt, int batch, hipStream_t s);
+                            int64_t sRn, const double *Rinv, const double *RinvT, int64_t sRi,
+                            int has_p, int recompute, double *C, double *G, int64_t sCG, double *Y,
+                            int64_t ldy, int64_t sY, int with_rt, int batch, hipStream_t s);
 
 // R[0:s, 0:w] -= Zn * Ua  (R block column-major ldr; Zn = -Z row-major s x w
 //                          with leading dim ldz, as stored by the reduction

@@ -207,12 +207,16 @@ __global__ __launch_bounds__(64) void k_tn(int64_t m, int p, int q, const double
 // 7} (which reach all 8 column blocks) and {2, 3, 4, 5} (column blocks 2..7).
 // Every wave issues 72 MFMAs per 16-row step and loads only the column
 // blocks its rows reach. Lane maps and the register ring as in k_tn.
+// SAME = false: the upper part of X^T Y for two different 128-column
+// operands (the adjoint's dQ^T Q): the same split, each half also loading
+// its four row blocks of X.
 __host__ __device__ constexpr int gram128_row(int half, int i) {
   return half ? 2 + i : (i < 2 ? i : 4 + i);
 }
 
-template <bool VEC>
+template <bool VEC, bool SAME>
 __global__ __launch_bounds__(64) void k_gram128(int64_t m, const double *__restrict__ X, int64_t ldx,
+                                                const double *__restrict__ Y, int64_t ldy,
                                                 double *__restrict__ part, int64_t rc,
                                                 const int *__restrict__ info) {
   if (*info) return;
@@ -227,9 +231,16 @@ __global__ __launch_bounds__(64) void k_gram128(int64_t m, const double *__restr
     constexpr int H = decltype(half_c)::value;
     constexpr int CB0 = H ? 2 : 0;  // first column block this half reads
     constexpr int NCB = 8 - CB0;
+    // SAME: one set of column lines serves both operands; otherwise the
+    // half's four row blocks of X are loaded beside Y's column blocks
+    constexpr int NA = SAME ? 0 : 4;
     const double *pc[NCB];
+    const double *pr[4];
 #pragma unroll
-    for (int u = 0; u < NCB; ++u) pc[u] = X + (int64_t)(16 * (CB0 + u) + cl) * ldx + rb + 4 * g;
+    for (int u = 0; u < NCB; ++u) pc[u] = Y + (int64_t)(16 * (CB0 + u) + cl) * ldy + rb + 4 * g;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      pr[i] = X + (int64_t)(16 * gram128_row(H, i) + cl) * ldx + rb + 4 * g;
 
     d4 acc[4][8];
 #pragma unroll
@@ -237,23 +248,27 @@ __global__ __launch_bounds__(64) void k_gram128(int64_t m, const double *__restr
 #pragma unroll
       for (int y = 0; y < 8; ++y) acc[i][y] = d4{0.0, 0.0, 0.0, 0.0};
 
-    auto load = [&](double (&d)[NCB][4], int64_t off) {
+    auto ld4 = [&](const double *ptr, double (&v)[4]) {
+      if (VEC) {
+        const double2 *xa = reinterpret_cast<const double2 *>(ptr);
+        const double2 a0 = xa[0], a1 = xa[1];
+        v[0] = a0.x;
+        v[1] = a0.y;
+        v[2] = a1.x;
+        v[3] = a1.y;
+      } else {
 #pragma unroll
-      for (int u = 0; u < NCB; ++u) {
-        if (VEC) {
-          const double2 *xa = reinterpret_cast<const double2 *>(pc[u] + off);
-          const double2 a0 = xa[0], a1 = xa[1];
-          d[u][0] = a0.x;
-          d[u][1] = a0.y;
-          d[u][2] = a1.x;
-          d[u][3] = a1.y;
-        } else {
-#pragma unroll
-          for (int s = 0; s < 4; ++s) d[u][s] = pc[u][off + s];
-        }
+        for (int s = 0; s < 4; ++s) v[s] = ptr[s];
       }
     };
-    auto compute = [&](const double (&d)[NCB][4]) {
+    typedef double Stage[NCB + NA][4];
+    auto load = [&](Stage &d, int64_t off) {
+#pragma unroll
+      for (int u = 0; u < NCB; ++u) ld4(pc[u] + off, d[u]);
+#pragma unroll
+      for (int i = 0; i < NA; ++i) ld4(pr[i] + off, d[NCB + i]);
+    };
+    auto compute = [&](const Stage &d) {
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -261,41 +276,69 @@ __global__ __launch_bounds__(64) void k_gram128(int64_t m, const double *__restr
 #pragma unroll
           for (int y = 0; y < 8; ++y) {
             const int x = gram128_row(H, i);
-            if (y >= x) acc[i][y] = mfma16x16x4(d[x - CB0][s], d[y - CB0][s], acc[i][y]);
+            if (y >= x) {
+              if constexpr (SAME)
+                acc[i][y] = mfma16x16x4(d[x - CB0][s], d[y - CB0][s], acc[i][y]);
+              else
+                acc[i][y] = mfma16x16x4(d[NCB + i][s], d[y - CB0][s], acc[i][y]);
+            }
           }
     };
 
-    double d0[NCB][4], d1[NCB][4], d2[NCB][4];
+    // three stages in the ring for one operand, two for two (the register
+    // budget); scheduling barriers as in k_tn
     if (nsteps > 0) {
       auto at = [&](int64_t st) -> int64_t { return 16 * (st < nsteps ? st : nsteps - 1); };
-      load(d0, 0);
-      load(d1, at(1));
-      int64_t it = 0;
-      for (; it + 3 <= nsteps; it += 3) {
-        load(d2, at(it + 2));
-        __builtin_amdgcn_sched_barrier(0);
-        compute(d0);
-        __builtin_amdgcn_sched_barrier(0);
-        load(d0, at(it + 3));
-        __builtin_amdgcn_sched_barrier(0);
-        compute(d1);
-        __builtin_amdgcn_sched_barrier(0);
-        load(d1, at(it + 4));
-        __builtin_amdgcn_sched_barrier(0);
-        compute(d2);
-        __builtin_amdgcn_sched_barrier(0);
+      if constexpr (SAME) {
+        Stage d0, d1, d2;
+        load(d0, 0);
+        load(d1, at(1));
+        int64_t it = 0;
+        for (; it + 3 <= nsteps; it += 3) {
+          load(d2, at(it + 2));
+          __builtin_amdgcn_sched_barrier(0);
+          compute(d0);
+          __builtin_amdgcn_sched_barrier(0);
+          load(d0, at(it + 3));
+          __builtin_amdgcn_sched_barrier(0);
+          compute(d1);
+          __builtin_amdgcn_sched_barrier(0);
+          load(d1, at(it + 4));
+          __builtin_amdgcn_sched_barrier(0);
+          compute(d2);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (it < nsteps) compute(d0);
+        if (it + 1 < nsteps) compute(d1);
+      } else {
+        Stage d0, d1;
+        load(d0, 0);
+        int64_t it = 0;
+        for (; it + 2 <= nsteps; it += 2) {
+          load(d1, at(it + 1));
+          __builtin_amdgcn_sched_barrier(0);
+          compute(d0);
+          __builtin_amdgcn_sched_barrier(0);
+          load(d0, at(it + 2));
+          __builtin_amdgcn_sched_barrier(0);
+          compute(d1);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (it < nsteps) compute(d0);
       }
-      if (it < nsteps) compute(d0);
-      if (it + 1 < nsteps) compute(d1);
     }
     const int64_t rt = rb + 16 * nsteps;
     if (rt < re) {  // ragged tail: rows rt + 4g + s < re only
       const int64_t off = 16 * nsteps;
+      Stage d;
 #pragma unroll
-      for (int u = 0; u < NCB; ++u)
+      for (int u = 0; u < NCB + NA; ++u)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) d0[u][s] = ((rt + 4 * g + s) < re) ? pc[u][off + s] : 0.0;
-      compute(d0);
+        for (int s = 0; s < 4; ++s) {
+          const double *ptr = (u < NCB) ? pc[u] : pr[u - NCB];
+          d[u][s] = ((rt + 4 * g + s) < re) ? ptr[off + s] : 0.0;
+        }
+      compute(d);
     }
 
     double *out = part + (size_t)c * 128 * 128;
@@ -431,13 +474,14 @@ static bool tn_use_wide(bool gram, int p, int q, int batch, int tile) {
   return !gram && batch == 1 && p >= kTile && q >= 2 * kTile && tile != kTileNarrow;
 }
 
-static bool tn_use_gram128(bool gram, int p, int q, int batch, bool same) {
-  return gram && same && p == 128 && q == 128 && batch == 1;
+static bool tn_use_gram128(bool gram, int p, int q, int batch) {
+  return gram && p == 128 && q == 128 && batch == 1;
 }
 
 int64_t tn_tiles(bool gram, int p, int q, bool same, int tile) {
   const int tp = (p + kTile - 1) / kTile, tq = (q + kTile - 1) / kTile;
-  if (tn_use_gram128(gram, p, q, 1, same)) return 2;
+  (void)same;
+  if (tile != kTileNarrow && tn_use_gram128(gram, p, q, 1)) return 2;
   if (tn_use_wide(gram, p, q, 1, tile)) return (int64_t)tp * ((q + 2 * kTile - 1) / (2 * kTile));
   return gram ? (int64_t)tp * (tp + 1) / 2 : (int64_t)tp * tq;
 }
@@ -449,12 +493,17 @@ hipError_t launch_tn(bool gram, int64_t m, int p, int q, const double *L, int64_
   const int tp = (p + kTile - 1) / kTile, tq = (q + kTile - 1) / kTile;
   const bool vec = (ldl % 2 == 0) && (ldr % 2 == 0) && ((uintptr_t)L % 16 == 0) &&
                    ((uintptr_t)Rt % 16 == 0) && (rc % 16 == 0) && (sL % 2 == 0) && (sRt % 2 == 0);
-  if (tn_use_gram128(gram, p, q, batch, L == Rt && ldl == ldr)) {
+  if (tn_use_gram128(gram, p, q, batch)) {
     const dim3 gg((unsigned)(2 * nch));
-    if (vec)
-      hipLaunchKernelGGL((k_gram128<true>), gg, dim3(64), 0, s, m, L, ldl, part, rc, info);
-    else
-      hipLaunchKernelGGL((k_gram128<false>), gg, dim3(64), 0, s, m, L, ldl, part, rc, info);
+    const bool same = L == Rt && ldl == ldr;
+#define CQR_G128(V, S_) \
+  hipLaunchKernelGGL((k_gram128<V, S_>), gg, dim3(64), 0, s, m, L, ldl, Rt, ldr, part, rc, info)
+    if (same) {
+      if (vec) CQR_G128(true, true); else CQR_G128(false, true);
+    } else {
+      if (vec) CQR_G128(true, false); else CQR_G128(false, false);
+    }
+#undef CQR_G128
     return hipGetLastError();
   }
   if (tn_use_wide(gram, p, q, batch, tile)) {
@@ -1018,8 +1067,17 @@ __global__ __launch_bounds__(128) void k_nn_wide(int64_t m, int p, int q, const 
                                                  int64_t ldy, const double *Cin, int64_t ldci,
                                                  double *C, int64_t ldc, int nct, double *C2,
                                                  int64_t ldc2, const int *__restrict__ info,
-                                                 const int *__restrict__ skip) {
+                                                 const int *__restrict__ skip, const double *L2,
+                                                 int64_t ldl2, int psplit, int64_t sL,
+                                                 int64_t sL2, int64_t sY, int64_t sC) {
   if (*info || (skip && *skip)) return;
+  {  // batch: matrix blockIdx.y (C2 and Cin only for single products)
+    const int64_t bi = blockIdx.y;
+    L += bi * sL;
+    L2 += bi * sL2;
+    Y += bi * sY;
+    C += bi * sC;
+  }
   constexpr int kCols = 16 * NX;
   const int nw = blockDim.x >> 6;  // waves (column tiles) per workgroup
   const int64_t lid = xcd_logical(blockIdx.x, gridDim.x);
@@ -1072,7 +1130,11 @@ __global__ __launch_bounds__(128) void k_nn_wide(int64_t m, int p, int q, const 
     if (FAST) {
       const double *yb = Y + (yc < q ? yc : 0) + (int64_t)g * ldy;
       const double *lb = L + (int64_t)g * ldl + rl;
+      const double *lb2 = L2 + (int64_t)g * ldl2 + rl;  // k >= psplit: column k - psplit of L2
       auto load = [&](double (&da)[4][NX], double (&db)[4][4], int kk) {
+        const bool first = kk < psplit;  // a whole k step lies in one source
+        const double *lbase = first ? lb + (int64_t)kk * ldl : lb2 + (int64_t)(kk - psplit) * ldl2;
+        const int64_t lld = first ? ldl : ldl2;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const double2 *py = reinterpret_cast<const double2 *>(yb + (int64_t)(kk + 4 * s) * ldy);
@@ -1082,7 +1144,7 @@ __global__ __launch_bounds__(128) void k_nn_wide(int64_t m, int p, int q, const 
             da[s][2 * h] = t.x;
             da[s][2 * h + 1] = t.y;
           }
-          const double2 *pl = reinterpret_cast<const double2 *>(lb + (int64_t)(kk + 4 * s) * ldl);
+          const double2 *pl = reinterpret_cast<const double2 *>(lbase + (int64_t)(4 * s) * lld);
           const double2 l0 = pl[0], l1 = pl[1];
           db[s][0] = l0.x;
           db[s][1] = l0.y;
@@ -1117,8 +1179,9 @@ __global__ __launch_bounds__(128) void k_nn_wide(int64_t m, int p, int q, const 
         for (int s = 0; s < 4; ++s) {
           const int k = kk + 4 * s + g;
           const bool kok = k < kend;
-          const double *py = Y + (int64_t)(kok ? k : 0) * ldy;
-          const double *pl = L + (int64_t)(kok ? k : 0) * ldl;
+          const int kc = kok ? k : 0;
+          const double *py = Y + (int64_t)kc * ldy;
+          const double *pl = (kc < psplit) ? L + (int64_t)kc * ldl : L2 + (int64_t)(kc - psplit) * ldl2;
 #pragma unroll
           for (int x = 0; x < NX; ++x) da[s][x] = (kok && yc + x < q) ? py[yc + x] : 0.0;
 #pragma unroll
@@ -1156,7 +1219,8 @@ __global__ __launch_bounds__(128) void k_nn_wide(int64_t m, int p, int q, const 
         }
       }
   };
-  if ((r0 + 64 <= m) && (kend % 16 == 0) && ((q % NX) == 0 || c0 + kCols <= q))
+  if ((r0 + 64 <= m) && (kend % 16 == 0) && (psplit % 16 == 0) &&
+      ((q % NX) == 0 || c0 + kCols <= q))
     body(std::true_type{});
   else
     body(std::false_type{});
@@ -1430,6 +1494,20 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
   const int wc = (slabs >= 4 || (!subtract && slabs == 3)) ? 4 : (slabs >= 2 ? 2 : 1);
   const int wr = 4 / wc;
   const int ncg = (slabs + wc - 1) / wc;
+  if (!subtract && !upper_y && C2 == nullptr && p % 16 == 0 && psplit % 16 == 0 && q > 64 &&
+      tile != kTileSlab && (ldl % 2 == 0) && (ldl2 % 2 == 0) && (ldc % 2 == 0) && (ldy % 2 == 0) &&
+      ((uintptr_t)L % 16 == 0) && ((uintptr_t)L2 % 16 == 0) && ((uintptr_t)C % 16 == 0) &&
+      ((uintptr_t)Y % 16 == 0) && (sL % 2 == 0) && (sL2 % 2 == 0) && (sY % 2 == 0) &&
+      (sC % 2 == 0) && batch <= 65535) {
+    // no input C, [L | L2] Y (the adjoint's second pass): one wave per
+    // 64 x 128 tile, the accumulators held over the whole inner dimension
+    const int nct = (q + 127) / 128;
+    const int64_t rts = (m + 63) / 64;
+    hipLaunchKernelGGL((k_nn_wide<8, false, false>), dim3((unsigned)(rts * nct), (unsigned)batch),
+                       dim3(64), 0, s, m, p, q, L, ldl, Y, ldy, nullptr, 0, C, ldc, nct, nullptr, 0,
+                       info, skip, L2, ldl2, psplit, sL, sL2, sY, sC);
+    return hipGetLastError();
+  }
   if (!subtract && !upper_y && C2 == nullptr && p <= kYsMaxK && p % 16 == 0 && psplit % 16 == 0 &&
       (ldl % 2 == 0) && (ldl2 % 2 == 0) && (ldc % 2 == 0) && ((uintptr_t)L % 16 == 0) &&
       ((uintptr_t)L2 % 16 == 0) && ((uintptr_t)C % 16 == 0) && (sL % 2 == 0) &&
@@ -1465,7 +1543,8 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
     const int64_t rts = (m + 63) / 64;
     hipLaunchKernelGGL((k_nn_wide<8, false, false>), dim3((unsigned)rts), dim3(64), 0, s, m, p, h,
                        L, ldl, Y + h, ldy, nullptr, 0, C + (int64_t)h * ldc, ldc, 1,
-                       C2 ? C2 + (int64_t)h * ldc2 : nullptr, ldc2, info, skip);
+                       C2 ? C2 + (int64_t)h * ldc2 : nullptr, ldc2, info, skip, L, ldl, p, 0, 0, 0,
+                       0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_nn(false, true, m, h, h, L, ldl, Y, ldy, nullptr, 0, C, ldc, info, s, nullptr, 0,
@@ -1480,10 +1559,12 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
     const int64_t rts = (m + 63) / 64;
     if (nx == 8)
       hipLaunchKernelGGL((k_nn_wide<8, false, true>), dim3((unsigned)rts), dim3(64 * nct), 0, s, m,
-                         p, q, L, ldl, Y, ldy, nullptr, 0, C, ldc, nct, C2, ldc2, info, skip);
+                         p, q, L, ldl, Y, ldy, nullptr, 0, C, ldc, nct, C2, ldc2, info, skip, L, ldl,
+                         p, 0, 0, 0, 0);
     else
       hipLaunchKernelGGL((k_nn_wide<4, false, true>), dim3((unsigned)rts), dim3(64 * nct), 0, s, m,
-                         p, q, L, ldl, Y, ldy, nullptr, 0, C, ldc, nct, C2, ldc2, info, skip);
+                         p, q, L, ldl, Y, ldy, nullptr, 0, C, ldc, nct, C2, ldc2, info, skip, L, ldl,
+                         p, 0, 0, 0, 0);
     return hipGetLastError();
   }
   if (!subtract && ncg != 1) return hipErrorInvalidValue;  // in-place needs one column group
@@ -1538,10 +1619,10 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
     const dim3 gw((unsigned)(rts * nct));
     if (nx == 8)
       hipLaunchKernelGGL((k_nn_wide<8, true, false>), gw, dim3(64), 0, s, m, p, q, L, ldl, Y, ldy,
-                         Cin, ldci, C, ldc, nct, nullptr, 0, info, skip);
+                         Cin, ldci, C, ldc, nct, nullptr, 0, info, skip, L, ldl, p, 0, 0, 0, 0);
     else
       hipLaunchKernelGGL((k_nn_wide<4, true, false>), gw, dim3(64), 0, s, m, p, q, L, ldl, Y, ldy,
-                         Cin, ldci, C, ldc, nct, nullptr, 0, info, skip);
+                         Cin, ldci, C, ldc, nct, nullptr, 0, info, skip, L, ldl, p, 0, 0, 0, 0);
     return hipGetLastError();
   }
   if (upd == kTileResident) {
@@ -1893,71 +1974,82 @@ hipError_t launch_chol_inv(const double *W, int w, double *uout, double *rblk, i
 // Small n x n kernels of the QR adjoint dA = (dQ + Q copyltu(M)) R^{-T},
 // M = R dR^T - dQ^T Q. One matrix per blockIdx.y (batched), n <= kMaxPanel.
 // ----------------------------------------------------------------------------
-// Rinv = R^{-1}, R column-major (ld n), Rinv row-major (ld n); one workgroup
-// per matrix.
-__global__ __launch_bounds__(kCholThreads) void k_tri_inv(const double *__restrict__ R, int n,
-                                                          int64_t sR, double *__restrict__ Rinv,
-                                                          int64_t sRi) {
-  extern __shared__ double S[];  // wp x wp, then the inverse's scratch
-  R += blockIdx.x * sR;
-  Rinv += blockIdx.x * sRi;
-  const int tid = threadIdx.x, nt = blockDim.x, wp = blocked_order(n);
-  for (int e = tid; e < wp * wp; e += nt) {
-    const int i = e / wp, j = e % wp;
-    S[e] = (i < n && j < n) ? ((i <= j) ? R[i + (int64_t)j * n] : 0.0) : (i == j ? 1.0 : 0.0);
+// Rinv = R^{-1} (R column-major, ld n; Rinv row-major, ld n) one column per wave: column j solves R x = e_j by back
+// substitution, sweeping the columns of R from the right (x_k = x_k / R_kk,
+// applied as a multiply by the pivot's reciprocal, then x_i -= R_ik x_k for
+// i < k: column k of R is read contiguously, and the columns eight steps
+// ahead are in flight meanwhile). Lane l holds
+// x_l, x_{l+64}, ... (n <= 256). Every column is independent, so a batch of
+// n x n inverses is n x batch waves: a 128 x 128 inverse takes a few
+// microseconds where one workgroup doing the whole matrix took ~0.1 ms (the
+// adjoint's critical path waited for it).
+__global__ __launch_bounds__(64) void k_tri_inv_cols(const double *__restrict__ R, int n,
+                                                     int64_t sR, double *__restrict__ Rinv,
+                                                     int64_t sRi, double *__restrict__ RinvT) {
+  constexpr int D = 8;  // columns of R in flight ahead of the sweep
+  R += blockIdx.y * sR;
+  Rinv += blockIdx.y * sRi;
+  if (RinvT) RinvT += blockIdx.y * sRi;
+  const int j = blockIdx.x, lane = threadIdx.x;
+  double x[4], rb[D][4];
+  auto load_col = [&](double (&v)[4], int k) {  // rows of column k (zeros when k < 0)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = lane + 64 * t;
+      v[t] = (k >= 0 && i <= k && i < n) ? R[i + (int64_t)k * n] : 0.0;
+    }
+  };
+  // the pivots' reciprocals (one IEEE division each, as LAPACK's unblocked
+  // inverse scales by them), so that the sweep's dependency chain per column
+  // is two shuffles, a multiply and an FMA
+  double dinv[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int i = lane + 64 * t;
+    x[t] = (i == j) ? 1.0 : 0.0;
+    dinv[t] = (i <= j) ? 1.0 / R[i + (int64_t)i * n] : 0.0;
   }
-  __syncthreads();
-  lds_upper_inverse_blocked(S, wp, S + wp * wp, S + wp * wp + 16 * wp);
-  for (int e = tid; e < n * n; e += nt) {
-    const int i = e / n, c = e % n;
-    Rinv[e] = (c < i) ? 0.0 : S[i * wp + c];
+#pragma unroll
+  for (int u = 0; u < D; ++u) load_col(rb[u], j - u);
+  for (int kb = j; kb >= 0; kb -= D) {
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      const int k = kb - u;
+      if (k >= 0) {
+        const int tk = k >> 6, lk = k & 63;
+        double xs = x[0], ds = dinv[0];
+#pragma unroll
+        for (int t = 1; t < 4; ++t)
+          if (tk == t) {
+            xs = x[t];
+            ds = dinv[t];
+          }
+        const double xk = __shfl(xs, lk) * __shfl(ds, lk);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = lane + 64 * t;
+          if (i == k) x[t] = xk;
+          else if (i < k) x[t] -= rb[u][t] * xk;
+        }
+        load_col(rb[u], k - D);
+      }
+    }
   }
-}
-
-// Rinv = R^{-1} for n > kLdsPanel: R padded with the identity into the
-// device scratch G (order 256, one per matrix), wide_upper_inverse there.
-__global__ __launch_bounds__(kWideThreads) void k_tri_inv_wide(const double *__restrict__ R, int n,
-                                                               int64_t sR, double *__restrict__ Rinv,
-                                                               int64_t sRi, double *__restrict__ G) {
-  extern __shared__ double S[];
-  const int tid = threadIdx.x, nt = blockDim.x, wp = blocked_order(n);
-  R += blockIdx.x * sR;
-  Rinv += blockIdx.x * sRi;
-  G += (int64_t)blockIdx.x * wp * wp;
-  for (int e = tid; e < wp * wp; e += nt) {
-    const int i = e / wp, j = e % wp;
-    G[e] = (i < n && j < n) ? ((i <= j) ? R[i + (int64_t)j * n] : 0.0) : (i == j ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  wide_upper_inverse(G, wp, S);
-  for (int e = tid; e < n * n; e += nt) {
-    const int i = e / n, c = e % n;
-    Rinv[e] = (c < i) ? 0.0 : G[(int64_t)i * wp + c];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int i = lane + 64 * t;
+    if (i < n) {
+      Rinv[(int64_t)i * n + j] = (i <= j) ? x[t] : 0.0;
+      if (RinvT) RinvT[(int64_t)j * n + i] = (i <= j) ? x[t] : 0.0;  // R^{-T}, row-major
+    }
   }
 }
 
 hipError_t launch_tri_inv(const double *R, int n, int64_t sR, double *Rinv, int64_t sRi, int batch,
-                          hipStream_t s, double *gwork) {
+                          hipStream_t s, double *RinvT) {
   if (n < 1 || n > kMaxPanel) return hipErrorInvalidValue;
-  const int wp = blocked_order(n);
-  if (n > kLdsPanel) {
-    if (!gwork) return hipErrorInvalidValue;
-    const size_t lds = (size_t)wide_lds_doubles(wp) * sizeof(double);
-    static const hipError_t attr = hipFuncSetAttribute(
-        (const void *)k_tri_inv_wide, hipFuncAttributeMaxDynamicSharedMemorySize,
-        (int)((size_t)wide_lds_doubles(kMaxPanel) * sizeof(double)));
-    if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(k_tri_inv_wide, dim3((unsigned)batch), dim3(kWideThreads), lds, s, R, n, sR,
-                       Rinv, sRi, gwork);
-    return hipGetLastError();
-  }
-  const size_t lds = (size_t)blocked_lds_doubles(wp) * sizeof(double);
-  static const hipError_t attr = hipFuncSetAttribute(
-      (const void *)k_tri_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
-      (int)((size_t)blocked_lds_doubles(kLdsPanel) * sizeof(double)));
-  if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(k_tri_inv, dim3((unsigned)batch), dim3(kCholThreads), lds, s, R, n, sR, Rinv,
-                     sRi);
+  hipLaunchKernelGGL(k_tri_inv_cols, dim3((unsigned)n, (unsigned)batch), dim3(64), 0, s, R, n, sR,
+                     Rinv, sRi, RinvT);
   return hipGetLastError();
 }
 
@@ -1999,17 +2091,19 @@ __global__ __launch_bounds__(256) void k_adj_c(int n, const double *__restrict__
 
 // G = C R^{-T}: G[k][c] = sum_{l >= c} C[k][l] Rinv[c][l]   (row-major)
 __global__ __launch_bounds__(256) void k_adj_g(int n, const double *__restrict__ C, int64_t sC,
-                                               const double *__restrict__ Rinv, int64_t sRi,
+                                               const double *__restrict__ RinvT, int64_t sRi,
                                                double *__restrict__ G, int64_t sG) {
   const int64_t bi = blockIdx.y;
   C += bi * sC;
-  Rinv += bi * sRi;
+  RinvT += bi * sRi;
   G += bi * sG;
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= n * n) return;
   const int k = e / n, c = e % n;
+  // G[k][c] = sum_l C[k][l] R^{-T}[l][c]: the lanes of a wave read one row
+  // of R^{-T} (row-major) contiguously
   double acc = 0.0;
-  for (int l = c; l < n; ++l) acc += C[k * n + l] * Rinv[c * n + l];
+  for (int l = c; l < n; ++l) acc += C[k * n + l] * RinvT[(int64_t)l * n + c];
   G[e] = acc;
 }
 
@@ -2017,18 +2111,20 @@ __global__ __launch_bounds__(256) void k_adj_g(int n, const double *__restrict__
 //   rows [0, n) (only if with_rt): R^{-T};  rows [off, off + n): G, or
 //   R^{-1} G when Q is recomputed from A (the pass then multiplies A).
 __global__ __launch_bounds__(256) void k_adj_y(int n, const double *__restrict__ G, int64_t sG,
-                                               const double *__restrict__ Rinv, int64_t sRi,
+                                               const double *__restrict__ Rinv,
+                                               const double *__restrict__ RinvT, int64_t sRi,
                                                int with_rt, int recompute, double *__restrict__ Y,
                                                int64_t ldy, int64_t sY) {
   const int64_t bi = blockIdx.y;
   G += bi * sG;
   Rinv += bi * sRi;
+  RinvT += bi * sRi;
   Y += bi * sY;
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= n * n) return;
   const int k = e / n, c = e % n;
   const int off = with_rt ? n : 0;
-  if (with_rt) Y[(int64_t)k * ldy + c] = (c <= k) ? Rinv[c * n + k] : 0.0;
+  if (with_rt) Y[(int64_t)k * ldy + c] = RinvT[(int64_t)k * n + c];  // R^{-T}: zero above the diagonal
   double g;
   if (recompute) {
     g = 0.0;
@@ -2040,17 +2136,18 @@ __global__ __launch_bounds__(256) void k_adj_y(int n, const double *__restrict__
 }
 
 hipError_t launch_adj_small(int n, const double *T, int64_t sT, const double *R, const double *dR,
-                            int64_t sRn, const double *Rinv, int64_t sRi, int has_p, int recompute,
-                            double *C, double *G, int64_t sCG, double *Y, int64_t ldy, int64_t sY,
-                            int with_rt, int batch, hipStream_t s) {
+                            int64_t sRn, const double *Rinv, const double *RinvT, int64_t sRi,
+                            int has_p, int recompute, double *C, double *G, int64_t sCG, double *Y,
+                            int64_t ldy, int64_t sY, int with_rt, int batch, hipStream_t s) {
   dim3 g((unsigned)((n * n + 255) / 256), (unsigned)batch), blk(256);
   hipLaunchKernelGGL(k_adj_c, g, blk, 0, s, n, T, sT, R, dR, sRn, Rinv, sRi, has_p, recompute, C, sCG);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_g, g, blk, 0, s, n, C, sCG, Rinv, sRi, G, sCG);
+  hipLaunchKernelGGL(k_adj_g, g, blk, 0, s, n, C, sCG, RinvT, sRi, G, sCG);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_y, g, blk, 0, s, n, G, sCG, Rinv, sRi, with_rt, recompute, Y, ldy, sY);
+  hipLaunchKernelGGL(k_adj_y, g, blk, 0, s, n, G, sCG, Rinv, RinvT, sRi, with_rt, recompute, Y, ldy,
+                     sY);
   return hipGetLastError();
 }
 

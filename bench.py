@@ -79,7 +79,11 @@ def bench_batched(steps: int, warmup: int):
     for p in probs:
         a = matgen.test_matrix(p.m, p.n, p.kappa, p.seed)
         mats.append(torch.from_numpy(np.ascontiguousarray(a.T)).to("cuda").t())
-    call = cqr.BatchedCall(mats, bs=[p.b for p in probs])
+    from paper_2405_04237_amd import tune
+    bs, tune_table = tune.tune_batched(mats, [p.b for p in probs], log=log)
+    chosen = {n: sorted({b for b, p in zip(bs, probs) if p.n == n}) for n in sorted({p.n for p in probs})}
+    log(f"batched: panel widths per column count {chosen}")
+    call = cqr.BatchedCall(mats, bs=bs)
     call.launch()
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
@@ -100,13 +104,14 @@ def bench_batched(steps: int, warmup: int):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     hh = sum(2.0 * p.m * p.n ** 2 - 2.0 * p.n ** 3 / 3 for p in probs)
-    nbytes = sum(24.0 * p.m * p.n + 24.0 * p.m * p.n ** 2 / p.b for p in probs)
+    nbytes = sum(24.0 * p.m * p.n + 24.0 * p.m * p.n ** 2 / b for p, b in zip(probs, bs))
     worst = max(measure.orthogonality(q) for q in call.q)
     info = int((call.info != 0).sum().item())
     return {"workload": f"{len(probs)} matrices, m in [2048, 65536], n in {{16,32,64,128}}, "
                         "b = min(ceil(n/2), 32), kappa log-uniform in [1e2, 1e14]",
             "ms": round(ms, 3), "value": round(hh / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
             "graph": True, "max_orthogonality": worst, "breakdowns": info,
+            "panel_width_per_n": {str(k): v for k, v in chosen.items()}, "tune": tune_table,
             "roofline": {"bound": "hbm", "achieved": round(nbytes / (ms * 1e-3) / 1e9, 1),
                          "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                          "frac": round(nbytes / (ms * 1e-3) / PEAK_HBM, 4),

@@ -234,7 +234,7 @@ int64_t cqr_default_panel(int64_t m, int64_t n, int schedule);
  * cqr_plan_batched (host shapes; allocates and synchronises, so call it
  * outside graph capture): h_m[i], h_n[i] the shape of matrix i, h_b[i] its
  * panel width (h_b == NULL or 0 = min(ceil(n / 2), 32); clamped to n). Limits of this
- * form: n <= 128, panel width <= 32; schedule must be CQR_SCHED_MOD
+ * form: n <= 128, panel width <= 32, m <= 2^33; schedule must be CQR_SCHED_MOD
  * (CQR_ERR_UNSUPPORTED otherwise).
  *
  * cqr_factor_batched enqueues a reset kernel (queue word, team counters) and

@@ -34,6 +34,7 @@ constexpr int kBB = kBatchMaxPanel * kBatchMaxPanel;
 struct Lds {
   double *y, *w, *ua, *ub, *ui, *s, *d;
   int *flag;
+  double *trash;  // a word that absorbs masked-off writes
 };
 __device__ inline Lds lds_layout(double *base) {
   Lds L;
@@ -45,7 +46,34 @@ __device__ inline Lds lds_layout(double *base) {
   L.s = L.ui + kBB + 64;
   L.d = L.s + kBB;
   L.flag = reinterpret_cast<int *>(L.d + kBatchMaxPanel);  // flag[0]: slot, flag[1]: team wait
+  L.trash = reinterpret_cast<double *>(L.flag + 8);           // inside the 64-byte flag area
   return L;
+}
+
+// The matrices' addresses are read from device arrays, so the compiler cannot
+// prove they point to global memory and would emit flat instructions, which
+// count against the LDS wait counter as well: every LDS read would then wait
+// for the whole load ring. Every matrix access goes through these
+// global-typed helpers instead.
+// Pairs of doubles use a plain vector type (HIP's double2 is a class whose
+// copy goes through a generic pointer) aligned to 8 bytes only: a column
+// with an odd leading dimension still moves two rows per 16-byte access
+// (global memory accesses need only 4-byte alignment).
+typedef double dpair __attribute__((ext_vector_type(2)));
+typedef dpair dpair8 __attribute__((aligned(8)));
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) dpair8 gdpair;
+__device__ __forceinline__ double gld(const double *p) { return *(const gdouble *)p; }
+__device__ __forceinline__ double2 gld2(const double *p) {
+  const dpair v = *(const gdpair *)p;
+  return double2{v.x, v.y};
+}
+__device__ __forceinline__ void gst(double *p, double v) { *(gdouble *)p = v; }
+__device__ __forceinline__ void gst2(double *p, double2 v) {
+  dpair w;
+  w.x = v.x;
+  w.y = v.y;
+  *(gdpair *)p = w;
 }
 
 // Global-memory writes made by one wave before the barrier are visible to
@@ -67,13 +95,15 @@ __device__ inline void wg_sync() {
 // Lane maps as in the single-matrix k_tn: lane (cl, g) feeds rows 4g..4g+3
 // of column 16 a + cl; D element e of block (a, b) is (16a + g + 4e, 16b + cl).
 // ---------------------------------------------------------------------------
-template <int NA, int NB>
+template <int NA, int NB, bool SAME>
 __device__ __forceinline__ void tn_run(int64_t m, int na, int nb, const double *A, int64_t lda,
-                                       const double *B, int64_t ldb, bool vec, double *out, int ldo,
-                                       bool trans) {
-  // 16-row steps per ring stage: a stage holds at most 24 doubles per lane,
-  // so that the whole kernel fits two workgroups per compute unit
-  constexpr int U = (NA + NB <= 3) ? 2 : 1;
+                                       const double *B, int64_t ldb, double *out, int ldo,
+                                       bool trans, double *trash) {
+  // SAME: B is A (a Gram matrix), so only A's columns are loaded and each
+  // loaded value feeds both operands
+  constexpr int NL = SAME ? NA : NA + NB;  // column blocks loaded per stage
+  // 16-row steps per ring stage: a stage holds at most 16 doubles per lane
+  constexpr int U = (NL <= 1) ? 4 : (NL <= 3 ? 2 : 1);
   constexpr int SR = 16 * U;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, cl = lane & 15;
   for (int e = tid; e < na * nb; e += kThreads) {
@@ -111,8 +141,12 @@ __device__ __forceinline__ void tn_run(int64_t m, int na, int nb, const double *
           for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
+              // entries outside na x nb go to the trash word (an address
+              // select rather than a lane mask per entry: those masks would
+              // stay live in scalar registers through the whole row loop)
               const int I = 16 * a + g + 4 * e, J = 16 * b + cl;
-              if (I < na && J < nb) out[trans ? J * ldo + I : I * ldo + J] += acc[a][b][e];
+              double *dst = (I < na && J < nb) ? out + (trans ? J * ldo + I : I * ldo + J) : trash;
+              *dst += acc[a][b][e];
             }
       }
       __syncthreads();
@@ -122,24 +156,19 @@ __device__ __forceinline__ void tn_run(int64_t m, int na, int nb, const double *
 #pragma unroll
       for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
   };
-  typedef double Stage[NA + NB][U][4];
+  typedef double Stage[NL][U][4];
   auto load = [&](Stage &v, int64_t off) {  // off: row offset of the round
 #pragma unroll
-    for (int c = 0; c < NA + NB; ++c) {
+    for (int c = 0; c < NL; ++c) {
       const double *p = (c < NA ? pa[c] : pb[c - NA]) + off;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (vec) {
-          const double2 x0 = reinterpret_cast<const double2 *>(p + 16 * u)[0];
-          const double2 x1 = reinterpret_cast<const double2 *>(p + 16 * u)[1];
-          v[c][u][0] = x0.x;
-          v[c][u][1] = x0.y;
-          v[c][u][2] = x1.x;
-          v[c][u][3] = x1.y;
-        } else {
-#pragma unroll
-          for (int s = 0; s < 4; ++s) v[c][u][s] = p[16 * u + s];
-        }
+        const double2 x0 = gld2(p + 16 * u);
+        const double2 x1 = gld2(p + 16 * u + 2);
+        v[c][u][0] = x0.x;
+        v[c][u][1] = x0.y;
+        v[c][u][2] = x1.x;
+        v[c][u][3] = x1.y;
       }
     }
   };
@@ -152,23 +181,43 @@ __device__ __forceinline__ void tn_run(int64_t m, int na, int nb, const double *
         for (int a = 0; a < NA; ++a)
 #pragma unroll
           for (int b = 0; b < NB; ++b)
-            acc[a][b] = mfma16x16x4(v[a][u][s], v[NA + b][u][s], acc[a][b]);
+            acc[a][b] = mfma16x16x4(v[a][u][s], v[SAME ? b : NA + b][u][s], acc[a][b]);
   };
 
-  const int64_t round_rows = 4 * SR;
-  const int64_t nfull = m / round_rows;               // rounds with every row present
-  const int64_t per_flush = kTnFlushRows / SR;        // rounds between flushes
+  // 32-bit round and tile counters (a matrix has at most 2^33 rows)
+  constexpr int round_rows = 4 * SR;
+  constexpr int per_flush = kTnFlushRows / SR;  // rounds between flushes
+  const int nfull = (int)(m / round_rows);      // rounds with every row present
   if (nfull > 0) {
-    auto at = [&](int64_t r) -> int64_t { return round_rows * (r < nfull ? r : nfull - 1); };
-    auto step = [&](const Stage &v, int64_t r) {
+    auto at = [&](int r) -> int64_t { return (int64_t)round_rows * (r < nfull ? r : nfull - 1); };
+    int since = 0;  // rounds since the last flush
+    auto step = [&](const Stage &v, int) {
       compute(v);
-      if ((r + 1) % per_flush == 0) flush();
+      if (++since == per_flush) {
+        flush();
+        since = 0;
+      }
     };
-    {
+    if constexpr (NL >= 5) {  // wide products: two stages (at least 40 MFMAs of cover each)
+      Stage v0, v1;
+      load(v0, 0);
+      int r = 0;
+      for (; r + 2 <= nfull; r += 2) {
+        load(v1, at(r + 1));
+        __builtin_amdgcn_sched_barrier(0);
+        step(v0, r);
+        __builtin_amdgcn_sched_barrier(0);
+        load(v0, at(r + 2));
+        __builtin_amdgcn_sched_barrier(0);
+        step(v1, r + 1);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (r < nfull) step(v0, r);
+    } else {
       Stage v0, v1, v2;
       load(v0, 0);
       load(v1, at(1));
-      int64_t r = 0;
+      int r = 0;
       for (; r + 3 <= nfull; r += 3) {
         load(v2, at(r + 2));
         __builtin_amdgcn_sched_barrier(0);
@@ -188,18 +237,20 @@ __device__ __forceinline__ void tn_run(int64_t m, int na, int nb, const double *
     }
   }
   // the last, partial round: rows past m contribute zeros
-  const int64_t rt = nfull * round_rows;
+  const int64_t rt = (int64_t)nfull * round_rows;
   if (rt < m) {
     Stage v;
 #pragma unroll
-    for (int c = 0; c < NA + NB; ++c) {
+    for (int c = 0; c < NL; ++c) {
       const double *p = (c < NA ? pa[c] : pb[c - NA]) + rt;
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int64_t row = rt + wave * SR + 16 * u + 4 * g + s;
-          v[c][u][s] = (row < m) ? p[16 * u + s] : 0.0;
+          double x = 0.0;
+          if (row < m) x = gld(p + 16 * u + s);
+          v[c][u][s] = x;
         }
     }
     compute(v);
@@ -210,20 +261,24 @@ __device__ __forceinline__ void tn_run(int64_t m, int na, int nb, const double *
 
 // One call site for every TN product of the factorisation: dispatch on the
 // block counts (A side <= 2 blocks: the panel; B side up to 8 blocks, 128
-// columns, taken in passes of at most 4 blocks: wider passes need more
-// accumulators than two workgroups per compute unit leave a wave).
+// columns, taken in passes of at most 4 blocks; a Gram matrix in one pass
+// with one operand stream).
 __device__ __forceinline__ void wg_tn(int64_t m, int na, int nb, const double *A, int64_t lda,
-                                   const double *B, int64_t ldb, double *out, int ldo, bool trans) {
-  const bool vec = (lda % 2 == 0) && (ldb % 2 == 0) && ((uintptr_t)A % 16 == 0) &&
-                   ((uintptr_t)B % 16 == 0);
+                                   const double *B, int64_t ldb, double *out, int ldo, bool trans,
+                                   double *trash) {
   const int ka = (na + 15) / 16;
+  if (A == B && na == nb) {
+    if (ka == 1) tn_run<1, 1, true>(m, na, nb, A, lda, B, ldb, out, ldo, trans, trash);
+    if (ka == 2) tn_run<2, 2, true>(m, na, nb, A, lda, B, ldb, out, ldo, trans, trash);
+    return;
+  }
   for (int j0 = 0; j0 < nb; j0 += 64) {
     const int nbp = (nb - j0 < 64) ? nb - j0 : 64;
     const int kb = (nbp + 15) / 16;
     const double *Bp = B + (int64_t)j0 * ldb;
     double *op = out + (trans ? (int64_t)j0 * ldo : j0);
-#define CQR_TN_CASE(X, Y)                                               \
-    if (ka == X && kb == Y) tn_run<X, Y>(m, na, nbp, A, lda, Bp, ldb, vec, op, ldo, trans);
+#define CQR_TN_CASE(X, Y) \
+    if (ka == X && kb == Y) tn_run<X, Y, false>(m, na, nbp, A, lda, Bp, ldb, op, ldo, trans, trash);
     CQR_TN_CASE(1, 1) CQR_TN_CASE(1, 2) CQR_TN_CASE(1, 3) CQR_TN_CASE(1, 4)
     CQR_TN_CASE(2, 1) CQR_TN_CASE(2, 2) CQR_TN_CASE(2, 3) CQR_TN_CASE(2, 4)
 #undef CQR_TN_CASE
@@ -234,37 +289,39 @@ __device__ __forceinline__ void wg_tn(int64_t m, int na, int nb, const double *A
 // Row-streaming NN product C = L Y (+ Cin when sub) over rows [0, m): L m x p
 // column-major, Y p x q row-major in LDS (ld ldy; reads up to 64 columns past
 // a tile's start stay inside the LDS region), Cin / C m x q column-major.
-// 32 x 64 tiles are dealt to the waves round-robin (tile t: row tile t / nct,
-// column tile t % nct). The k steps of a wave's consecutive full tiles form
+// 32 x 16 NX tiles (NX = 1, 2 or 4: the narrowest that covers q, or 4) are
+// dealt to the waves round-robin (tile t: row tile t / nct, column tile
+// t % nct). The k steps of a wave's consecutive full tiles form
 // one stream through a three-deep register ring; a tile's first stage also
 // carries its Cin. C may alias L when q <= 64 (a wave reads its tile's rows
 // fully before writing them, and no other wave touches those rows); Cin may
-// equal C. Lane maps as in k_nn with two rows per lane.
+// equal C. Lane maps as in k_nn with two rows per lane: lane (cl, g) holds
+// rows r0 + 2 cl + {0, 1} and columns c0 + NX (g + 4 e) + x of the tile.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, int64_t ldl,
-                                   const double *Y, int ldy, const double *Cin, int64_t ldci,
-                                   double *C, int64_t ldc, bool sub) {
+template <int NX, bool SUB>
+__device__ __forceinline__ void nn_run(int64_t m, int p, int q, const double *L, int64_t ldl,
+                                       const double *Y, int ldy, const double *Cin, int64_t ldci,
+                                       double *C, int64_t ldc) {
+  constexpr int TW = 16 * NX;  // tile width
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, cl = lane & 15;
-  const bool vec = (ldl % 2 == 0) && (ldc % 2 == 0) && (!sub || ldci % 2 == 0) &&
-                   ((uintptr_t)L % 16 == 0) && ((uintptr_t)C % 16 == 0) &&
-                   (!sub || (uintptr_t)Cin % 16 == 0);
-  const int nct = (q + 63) / 64;
+  const int nct = (q + TW - 1) / TW;
   const int nk = (p + 15) / 16;
-  const int64_t nrt_full = m / 32;
-  const int64_t nt_full = nrt_full * nct;
-  const int64_t mine = (nt_full > wave) ? (nt_full - wave + 3) / 4 : 0;  // full tiles of this wave
-  const int64_t T = mine * nk;                                            // steps
+  // 32-bit tile and step counters (a matrix has at most 2^33 rows)
+  const int nrt_full = (int)(m / 32);
+  const int nt_full = nrt_full * nct;
+  const int mine = (nt_full > wave) ? (nt_full - wave + 3) / 4 : 0;  // full tiles of this wave
+  const int T = mine * nk;                                            // steps
 
   struct Stage {
     double l[4][2];  // L[rl + y][k], k = 16 ks + 4 s + g
   };
-  d4 acc[4][2];
-  double cn[4][4][2];  // Cin[rl + y][c0 + 4 g + 16 e + x] of the next tile to start
+  d4 acc[NX][2];
+  double cn[4][NX][2];  // Cin[rl + y][c0 + NX (g + 4 e) + x] of the next tile to start
 
-  auto tile_of = [&](int64_t i, int64_t &r0, int &c0) {  // i-th tile of this wave
-    const int64_t t = wave + 4 * i;
-    r0 = (t / nct) * 32;
-    c0 = (int)(t % nct) * 64;
+  auto tile_of = [&](int i, int64_t &r0, int &c0) {  // i-th tile of this wave
+    const int t = wave + 4 * i;
+    r0 = (int64_t)(t / nct) * 32;
+    c0 = (int)(t % nct) * TW;
   };
   auto load_l = [&](double (&l)[4][2], int64_t rl, int ks, int64_t rows_left) {
 #pragma unroll
@@ -272,34 +329,36 @@ __device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, 
       const int k = 16 * ks + 4 * s + g;
       const double *pl = L + (int64_t)(k < p ? k : p - 1) * ldl + rl;
       double x0, x1;
-      if (vec && rows_left >= 2) {
-        const double2 t = *reinterpret_cast<const double2 *>(pl);
+      if (rows_left >= 2) {
+        const double2 t = gld2(pl);
         x0 = t.x;
         x1 = t.y;
       } else {
-        x0 = (rows_left > 0) ? pl[0] : 0.0;
-        x1 = (rows_left > 1) ? pl[1] : 0.0;
+        x0 = x1 = 0.0;
+        if (rows_left > 0) x0 = gld(pl);
+        if (rows_left > 1) x1 = gld(pl + 1);
       }
       l[s][0] = (k < p) ? x0 : 0.0;
       l[s][1] = (k < p) ? x1 : 0.0;
     }
   };
-  auto load_c = [&](double (&cv)[4][4][2], int64_t rl, int c0, int64_t rows_left) {
+  auto load_c = [&](double (&cv)[4][NX][2], int64_t rl, int c0, int64_t rows_left) {
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        const int col = c0 + 4 * g + 16 * e + x;
+      for (int x = 0; x < NX; ++x) {
+        const int col = c0 + NX * (g + 4 * e) + x;
         double x0 = 0.0, x1 = 0.0;
-        if (sub && col < q) {
-          const double *pc = Cin + (int64_t)col * ldci + rl;
-          if (vec && rows_left >= 2) {
-            const double2 t = *reinterpret_cast<const double2 *>(pc);
+        if constexpr (SUB) {
+          // columns past q read column q - 1: they reach only outputs never stored
+          const double *pc = Cin + (int64_t)(col < q ? col : q - 1) * ldci + rl;
+          if (rows_left >= 2) {
+            const double2 t = gld2(pc);
             x0 = t.x;
             x1 = t.y;
           } else {
-            x0 = (rows_left > 0) ? pc[0] : 0.0;
-            x1 = (rows_left > 1) ? pc[1] : 0.0;
+            if (rows_left > 0) x0 = gld(pc);
+            if (rows_left > 1) x1 = gld(pc + 1);
           }
         }
         cv[e][x][0] = x0;
@@ -307,44 +366,52 @@ __device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, 
       }
   };
   auto mma = [&](const double (&l)[4][2], int ks, int c0) {
-    const double *yl = Y + c0 + 4 * cl;
+    const double *yl = Y + c0 + NX * cl;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int k = 16 * ks + 4 * s + g;
-      double ya[4];
+      double ya[NX];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
+      for (int x = 0; x < NX; ++x) {
         const double yv = yl[(k < p ? k : 0) * ldy + x];
         ya[x] = (k < p) ? yv : 0.0;
       }
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int x = 0; x < NX; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x4(ya[x], l[s][y], acc[x][y]);
     }
   };
-  auto store = [&](int64_t rl, int c0, int64_t rows_left) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        const int col = c0 + 4 * g + 16 * e + x;
-        if (col < q) {
-          double *pc = C + (int64_t)col * ldc + rl;
-          if (vec && rows_left >= 2) {
-            *reinterpret_cast<double2 *>(pc) = double2{acc[x][0][e], acc[x][1][e]};
-          } else {
-            if (rows_left > 0) pc[0] = acc[x][0][e];
-            if (rows_left > 1) pc[1] = acc[x][1][e];
-          }
-        }
-      }
+  auto store_one = [&](int64_t rl, int col, int x, int e, int64_t rows_left) {
+    double *pc = C + (int64_t)col * ldc + rl;
+    if (rows_left >= 2) {
+      gst2(pc, double2{acc[x][0][e], acc[x][1][e]});
+    } else {
+      if (rows_left > 0) gst(pc, acc[x][0][e]);
+      if (rows_left > 1) gst(pc + 1, acc[x][1][e]);
+    }
   };
-  auto init_acc = [&](const double (&cv)[4][4][2]) {
+  auto store = [&](int64_t rl, int c0, int64_t rows_left) {
+    if (c0 + TW <= q) {  // every column of the tile is stored (uniform)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int x = 0; x < NX; ++x) store_one(rl, c0 + NX * (g + 4 * e) + x, x, e, rows_left);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int x = 0; x < NX; ++x) {
+          const int col = c0 + NX * (g + 4 * e) + x;
+          if (col < q) store_one(rl, col, x, e, rows_left);
+        }
+    }
+  };
+  auto init_acc = [&](const double (&cv)[4][NX][2]) {
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
+      for (int x = 0; x < NX; ++x) {
         acc[x][0][e] = cv[e][x][0];
         acc[x][1][e] = cv[e][x][1];
       }
@@ -353,10 +420,9 @@ __device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, 
   if (T > 0) {
     // load cursor (L only: a tile's Cin is loaded when the tile before it
     // starts, into cn, so the ring stages stay small)
-    int64_t li = 0, lr0;
-    int lc0, lks = 0;
+    int li = 0, lc0, lks = 0, lt = 0;
+    int64_t lr0;
     tile_of(0, lr0, lc0);
-    int64_t lt = 0;
     auto load = [&](Stage &st) {
       const int64_t rl = lr0 + 2 * cl;
       load_l(st.l, rl, lks, 2);
@@ -369,8 +435,8 @@ __device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, 
       }
     };
     // compute cursor
-    int64_t ci = 0, cr0;
-    int cc0, cks = 0;
+    int ci = 0, cc0, cks = 0;
+    int64_t cr0;
     tile_of(0, cr0, cc0);
     load_c(cn, cr0 + 2 * cl, cc0, 2);
     auto step = [&](const Stage &st) {
@@ -393,7 +459,7 @@ __device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, 
     Stage s0, s1, s2;
     load(s0);
     load(s1);
-    int64_t t = 0;
+    int t = 0;
     for (; t + 3 <= T; t += 3) {
       load(s2);
       __builtin_amdgcn_sched_barrier(0);
@@ -412,11 +478,11 @@ __device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, 
     if (t + 1 < T) step(s1);
   }
   // the last, partial row tile (fewer than 32 rows), masked
-  if (nrt_full * 32 < m) {
+  if ((int64_t)nrt_full * 32 < m) {
     for (int ct = 0; ct < nct; ++ct) {
-      if ((int)((nt_full + ct) % 4) != wave) continue;
-      const int64_t r0 = nrt_full * 32;
-      const int c0 = ct * 64;
+      if ((nt_full + ct) % 4 != wave) continue;
+      const int64_t r0 = (int64_t)nrt_full * 32;
+      const int c0 = ct * TW;
       const int64_t rl = r0 + 2 * cl;
       const int64_t left = m - rl;
       Stage st;
@@ -430,6 +496,30 @@ __device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, 
     }
   }
   wg_sync();
+}
+
+// Dispatch on the tile width (the narrowest of 16, 32, 64 columns that
+// covers q, else 64) and on SUB (C = Cin + L Y, Y then holding the negated
+// factor, or C = L Y).
+template <int NX>
+__device__ __forceinline__ void nn_sub(int64_t m, int p, int q, const double *L, int64_t ldl,
+                                       const double *Y, int ldy, const double *Cin, int64_t ldci,
+                                       double *C, int64_t ldc, bool sub) {
+  if (sub)
+    nn_run<NX, true>(m, p, q, L, ldl, Y, ldy, Cin, ldci, C, ldc);
+  else
+    nn_run<NX, false>(m, p, q, L, ldl, Y, ldy, Cin, ldci, C, ldc);
+}
+
+__device__ __forceinline__ void wg_nn(int64_t m, int p, int q, const double *L, int64_t ldl,
+                                   const double *Y, int ldy, const double *Cin, int64_t ldci,
+                                   double *C, int64_t ldc, bool sub) {
+  if (q <= 16)
+    nn_sub<1>(m, p, q, L, ldl, Y, ldy, Cin, ldci, C, ldc, sub);
+  else if (q <= 32)
+    nn_sub<2>(m, p, q, L, ldl, Y, ldy, Cin, ldci, C, ldc, sub);
+  else
+    nn_sub<4>(m, p, q, L, ldl, Y, ldy, Cin, ldci, C, ldc, sub);
 }
 
 // Spin limit of a team barrier (s_sleep 2 per try, about 3 s in all): a
@@ -449,11 +539,11 @@ struct Team {
 // out (LDS, count doubles: this member's partial sum over its rows) := the
 // sum of all members' partials, in member order, identical in every member.
 // Returns false if a partner did not arrive within the spin limit.
-__device__ bool team_reduce(const Lds &S, Team &T, double *out, int count) {
+__device__ __forceinline__ bool team_reduce(const Lds &S, Team &T, double *out, int count) {
   const int tid = threadIdx.x;
   double *buf = T.part + (int64_t)(T.barriers & 1) * T.team * kTeamSlot;
   double *mine = buf + (int64_t)T.member * kTeamSlot;
-  for (int e = tid; e < count; e += kThreads) mine[e] = out[e];
+  for (int e = tid; e < count; e += kThreads) gst(mine + e, out[e]);
   __threadfence();  // release this member's partial (all L2s)
   __syncthreads();
   if (tid == 0) {
@@ -475,7 +565,7 @@ __device__ bool team_reduce(const Lds &S, Team &T, double *out, int count) {
   if (ok) {
     for (int e = tid; e < count; e += kThreads) {
       double x = 0.0;
-      for (int k = 0; k < T.team; ++k) x += buf[(int64_t)k * kTeamSlot + e];
+      for (int k = 0; k < T.team; ++k) x += gld(buf + (int64_t)k * kTeamSlot + e);
       out[e] = x;
     }
   }
@@ -522,7 +612,7 @@ __device__ __forceinline__ void wg_r_upper_product(double *R, int n, int r0, int
     const int i = e % w, c = e / w;
     double acc = 0.0;
     for (int k = i; k <= c; ++k) acc += Ub[i * w + k] * Ua[k * w + c];
-    R[(r0 + i) + (int64_t)(r0 + c) * n] = (i <= c) ? acc : 0.0;
+    gst(R + (r0 + i) + (int64_t)(r0 + c) * n, (i <= c) ? acc : 0.0);
   }
 }
 
@@ -536,7 +626,7 @@ __device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int n, int b, const doub
   const double *A = A0 + T.r0;
   double *Q = Q0 + T.r0;
   if (lead)
-    for (int e = tid; e < n * n; e += kThreads) R[e] = 0.0;
+    for (int e = tid; e < n * n; e += kThreads) gst(R + e, 0.0);
   const int w0 = n < b ? n : b;
   int s = 0;  // first column of the current panel
   int w = w0;
@@ -546,8 +636,10 @@ __device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int n, int b, const doub
     int op = 0;  // 1 = TN, 2 = NN
     int64_t tm = m;
     int ta = 0, tb = 0, tldo = 0, np = 0, nq = 0, nldy = 0;
-    const double *tA = nullptr, *tB = nullptr, *nL = nullptr, *nY = nullptr, *nCin = nullptr;
-    double *tout = nullptr, *nC = nullptr;
+    // LDS operands start at an LDS address (not null), so that the compiler
+    // still sees every value they may take as LDS and emits LDS instructions
+    const double *tA = nullptr, *tB = nullptr, *nL = nullptr, *nY = S.y, *nCin = nullptr;
+    double *tout = S.w, *nC = nullptr;
     bool ttrans = false, nsub = false;
     const int ps = s - b, nr = n - s;
     double *Xj = Q + (int64_t)s * lda;
@@ -574,7 +666,7 @@ __device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int n, int b, const doub
         const int ldy = (int)padded_ld(nr);
         for (int e = tid; e < b * nr; e += kThreads) {
           const int i = e / nr, j = e % nr;
-          if (lead) R[(ps + i) + (int64_t)(s + j) * n] = S.y[i * ldy + j];
+          if (lead) gst(R + (ps + i) + (int64_t)(s + j) * n, S.y[i * ldy + j]);
           S.y[i * ldy + j] = -S.y[i * ldy + j];
         }
         __syncthreads();
@@ -596,7 +688,8 @@ __device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int n, int b, const doub
           const int i = e % s, c = e / s;
           double acc = 0.0;
           for (int k = 0; k <= c; ++k) acc += S.y[i * ldw + k] * S.ua[k * w + c];
-          R[i + (int64_t)(s + c) * n] += acc;
+          double *pr = R + i + (int64_t)(s + c) * n;
+          gst(pr, gld(pr) + acc);
         }
         __syncthreads();
         for (int e = tid; e < s * ldw; e += kThreads) S.y[e] = -S.y[e];
@@ -615,7 +708,7 @@ __device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int n, int b, const doub
         break;
     }
     if (op == 1) {
-      wg_tn(tm, ta, tb, tA, lda, tB, lda, tout, tldo, ttrans);
+      wg_tn(tm, ta, tb, tA, lda, tB, lda, tout, tldo, ttrans, S.trash);
       if (T.team > 1 && !team_reduce(S, T, tout, (ttrans ? tb : ta) * tldo)) return -1;
     } else if (op == 2) {
       wg_nn(tm, np, nq, nL, lda, nY, nldy, nCin ? nCin : nC, lda, nC, lda, nsub);

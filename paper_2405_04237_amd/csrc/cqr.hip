@@ -978,7 +978,8 @@ int cqr_plan_batched(int64_t batch, const int64_t *h_m, const int64_t *h_n, cons
   std::vector<int> n(batch), b(batch);
   double flops = 0, bytes = 0;
   for (int64_t i = 0; i < batch; ++i) {
-    if (h_n[i] < 1 || m[i] < h_n[i] || m[i] > (int64_t(1) << 40)) return CQR_ERR_ARG;
+    if (h_n[i] < 1 || m[i] < h_n[i]) return CQR_ERR_ARG;
+    if (m[i] > (int64_t(1) << 33)) return CQR_ERR_UNSUPPORTED;  // the kernel counts rows in 32 bits
     const int64_t bi = h_b ? h_b[i] : 0;
     if (bi < 0) return CQR_ERR_ARG;
     // default: two or more panels, at most kBatchMaxPanel wide (a single panel

@@ -132,6 +132,11 @@ __device__ __forceinline__ void tn_run(int64_t m, int na, int nb, const double *
     for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
   auto flush = [&]() {  // out += acc, wave 0 first; acc = 0
+    // the lane coordinates pass through an empty asm statement so that the
+    // destination addresses are formed here, not hoisted out of the row
+    // loop where they would stay live in registers
+    int fg = g, fcl = cl;
+    asm volatile("" : "+v"(fg), "+v"(fcl));
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
       if (wave == w) {
@@ -144,7 +149,7 @@ __device__ __forceinline__ void tn_run(int64_t m, int na, int nb, const double *
               // entries outside na x nb go to the trash word (an address
               // select rather than a lane mask per entry: those masks would
               // stay live in scalar registers through the whole row loop)
-              const int I = 16 * a + g + 4 * e, J = 16 * b + cl;
+              const int I = 16 * a + fg + 4 * e, J = 16 * b + fcl;
               double *dst = (I < na && J < nb) ? out + (trans ? J * ldo + I : I * ldo + J) : trash;
               *dst += acc[a][b][e];
             }

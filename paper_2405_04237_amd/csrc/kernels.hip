@@ -2074,15 +2074,21 @@ __global__ __launch_bounds__(256) void k_adj_c(int n, const double *__restrict__
   if (e >= n * n) return;
   const int i = e / n, j = e % n;
   if (i < j) return;
+  // the sums run in order of k; unrolling lets each thread keep several
+  // loads in flight (the loops are latency-bound, not arithmetic-bound)
   double rdr = 0.0;
-  if (dR)
+  if (dR) {
+#pragma unroll 8
     for (int k = i; k < n; ++k) rdr += R[i + (int64_t)k * n] * dR[j + (int64_t)k * n];
+  }
   double pv = 0.0;
   if (has_p) {
-    if (recompute)
+    if (recompute) {
+#pragma unroll 8
       for (int k = 0; k <= j; ++k) pv += T[k * n + i] * Rinv[k * n + j];
-    else
+    } else {
       pv = T[j * n + i];
+    }
   }
   const double mv = rdr - pv;
   C[i * n + j] = mv;
@@ -2103,8 +2109,31 @@ __global__ __launch_bounds__(256) void k_adj_g(int n, const double *__restrict__
   // G[k][c] = sum_l C[k][l] R^{-T}[l][c]: the lanes of a wave read one row
   // of R^{-T} (row-major) contiguously
   double acc = 0.0;
+#pragma unroll 8
   for (int l = c; l < n; ++l) acc += C[k * n + l] * RinvT[(int64_t)l * n + c];
   G[e] = acc;
+}
+
+// G = C R^{-T} as k_adj_g, written straight into the streaming pass's right
+// operand (rows [off, off + n) of Y; rows [0, n) get R^{-T} when with_rt):
+// the form used when Q is given, where Y's lower block is G itself.
+__global__ __launch_bounds__(256) void k_adj_gy(int n, const double *__restrict__ C, int64_t sC,
+                                                const double *__restrict__ RinvT, int64_t sRi,
+                                                int with_rt, double *__restrict__ Y, int64_t ldy,
+                                                int64_t sY) {
+  const int64_t bi = blockIdx.y;
+  C += bi * sC;
+  RinvT += bi * sRi;
+  Y += bi * sY;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * n) return;
+  const int k = e / n, c = e % n;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int l = c; l < n; ++l) acc += C[k * n + l] * RinvT[(int64_t)l * n + c];
+  const int off = with_rt ? n : 0;
+  if (with_rt) Y[(int64_t)k * ldy + c] = RinvT[(int64_t)k * n + c];
+  Y[(int64_t)(off + k) * ldy + c] = acc;
 }
 
 // The right operand of the streaming pass, row-major with leading dim ldy:
@@ -2143,6 +2172,10 @@ hipError_t launch_adj_small(int n, const double *T, int64_t sT, const double *R,
   hipLaunchKernelGGL(k_adj_c, g, blk, 0, s, n, T, sT, R, dR, sRn, Rinv, sRi, has_p, recompute, C, sCG);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (!recompute) {
+    hipLaunchKernelGGL(k_adj_gy, g, blk, 0, s, n, C, sCG, RinvT, sRi, with_rt, Y, ldy, sY);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_adj_g, g, blk, 0, s, n, C, sCG, RinvT, sRi, G, sCG);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

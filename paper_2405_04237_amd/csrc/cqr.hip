@@ -927,8 +927,10 @@ int cqr_backward_batched(int64_t batch, int64_t m, int64_t n, const double *Q, c
   // pass 2: dA = [dQ | S] [R^{-T}; G]   (or S G when dQ is absent)
   if (dQ) {
     e = timed(s, CQR_K_UPDATE, bf * 4.0 * mf * nf * nf, 24.0 * bf * mf * nf, [&] {
+      // Y's upper block is R^{-T}: lower triangular
       return cqr::launch_nn(false, false, m, 2 * ni, ni, dQ, lda, Y, lay.ldy, nullptr, 0, dA, lda,
-                            info, s, S, lda, ni, b, stride, stride, sy, 0, stride);
+                            info, s, S, lda, ni, b, stride, stride, sy, 0, stride, nullptr, 0,
+                            nullptr, cqr::kTileAuto, true);
     });
   } else {
     e = timed(s, CQR_K_UPDATE, bf * 2.0 * mf * nf * nf, 16.0 * bf * mf * nf, [&] {

@@ -67,13 +67,16 @@ int64_t tn_tiles(bool gram, int p, int q, bool same = false, int tile = kTileAut
 // an in-place product).
 // tile: the kernel variant of a single-matrix update (subtract = true,
 // batch = 1, no L2, no C2); every variant gives the same bits.
+// lower_first: rows k < psplit of Y are lower triangular (Y[k][c] = 0 for
+// c > k, exact zeros), so the wide product of an input-free [L | L2] Y may
+// skip their zero blocks (the adjoint's [dQ | Q] [R^{-T}; G]).
 hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const double *L,
                      int64_t ldl, const double *Y, int64_t ldy, const double *Cin, int64_t ldci,
                      double *C, int64_t ldc, const int *info, hipStream_t s,
                      const double *L2 = nullptr, int64_t ldl2 = 0, int psplit = 0, int batch = 1,
                      int64_t sL = 0, int64_t sL2 = 0, int64_t sY = 0, int64_t sCin = 0,
                      int64_t sC = 0, double *C2 = nullptr, int64_t ldc2 = 0,
-                     const int *skip = nullptr, int tile = kTileAuto);
+                     const int *skip = nullptr, int tile = kTileAuto, bool lower_first = false);
 
 // True when launch_nn runs a single-matrix subtract = true product through
 // the short-inner-dimension kernel (Y staged in LDS); false: the general one.

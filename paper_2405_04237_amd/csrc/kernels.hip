@@ -1061,7 +1061,7 @@ __global__ __launch_bounds__(256, 1) void k_upd_lr(int64_t mfull, int p, int q, 
 // add exact zeros), so all three agree bit for bit. C2 (optional) receives
 // the same values as C.
 // ----------------------------------------------------------------------------
-template <int NX, bool SUB, bool TRI>
+template <int NX, bool SUB, bool TRI, bool LFIRST = false>
 __global__ __launch_bounds__(128) void k_nn_wide(int64_t m, int p, int q, const double *L,
                                                  int64_t ldl, const double *__restrict__ Y,
                                                  int64_t ldy, const double *Cin, int64_t ldci,
@@ -1088,6 +1088,9 @@ __global__ __launch_bounds__(128) void k_nn_wide(int64_t m, int p, int q, const 
   const int lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
   const int64_t rl = r0 + 4 * cl;  // this lane's 4 rows
   const int yc = c0 + NX * cl;     // this lane's NX columns of Y
+  // column of A-operand / D row i in column block x: NX-interleaved, or (LFIRST)
+  // block x = the 16 contiguous columns c0 + 16 x .. c0 + 16 x + 15
+  auto col_of = [&](int x, int i) -> int { return LFIRST ? c0 + 16 * x + i : c0 + NX * i + x; };
 
   // FAST: every row of the tile exists, p % 16 == 0 and each lane's NX
   // columns are all < q or all >= q. The two forms are separate code paths
@@ -1111,7 +1114,7 @@ __global__ __launch_bounds__(128) void k_nn_wide(int64_t m, int p, int q, const 
         d4 v;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int col = c0 + NX * (g + 4 * e) + x;
+          const int col = col_of(x, g + 4 * e);
           const double *pc = Cin + (int64_t)(col < q ? col : 0) * ldci + rl + y;
           v[e] = (FAST || (col < q && rl + y < m)) ? *pc : 0.0;
         }
@@ -1119,16 +1122,22 @@ __global__ __launch_bounds__(128) void k_nn_wide(int64_t m, int p, int q, const 
       }
       __builtin_amdgcn_sched_barrier(0);
     }
-    auto compute = [&](const double (&da)[4][NX], const double (&db)[4][4]) {
+    // LFIRST: the first source's rows of Y (k < psplit) are lower triangular
+    // (Y[k][c] = 0 for c > k), so block x gets nothing from a k step that
+    // ends below column 16 x: those MFMAs would add exact zeros
+    auto compute = [&](const double (&da)[4][NX], const double (&db)[4][4], int kk) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int x = 0; x < NX; ++x) {
+        if (LFIRST && kk + 16 <= psplit && 16 * x > kk + 15) continue;
 #pragma unroll
-        for (int x = 0; x < NX; ++x)
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
           for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x4(da[s][x], db[s][y], acc[x][y]);
+      }
     };
     if (FAST) {
-      const double *yb = Y + (yc < q ? yc : 0) + (int64_t)g * ldy;
+      const double *yb = LFIRST ? Y + c0 + cl + (int64_t)g * ldy
+                                : Y + (yc < q ? yc : 0) + (int64_t)g * ldy;
       const double *lb = L + (int64_t)g * ldl + rl;
       const double *lb2 = L2 + (int64_t)g * ldl2 + rl;  // k >= psplit: column k - psplit of L2
       auto load = [&](double (&da)[4][NX], double (&db)[4][4], int kk) {
@@ -1137,12 +1146,18 @@ __global__ __launch_bounds__(128) void k_nn_wide(int64_t m, int p, int q, const 
         const int64_t lld = first ? ldl : ldl2;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          const double2 *py = reinterpret_cast<const double2 *>(yb + (int64_t)(kk + 4 * s) * ldy);
+          if constexpr (LFIRST) {
+            const double *py = yb + (int64_t)(kk + 4 * s) * ldy;
 #pragma unroll
-          for (int h = 0; h < NX / 2; ++h) {
-            const double2 t = py[h];
-            da[s][2 * h] = t.x;
-            da[s][2 * h + 1] = t.y;
+            for (int x = 0; x < NX; ++x) da[s][x] = py[16 * x];
+          } else {
+            const double2 *py = reinterpret_cast<const double2 *>(yb + (int64_t)(kk + 4 * s) * ldy);
+#pragma unroll
+            for (int h = 0; h < NX / 2; ++h) {
+              const double2 t = py[h];
+              da[s][2 * h] = t.x;
+              da[s][2 * h + 1] = t.y;
+            }
           }
           const double2 *pl = reinterpret_cast<const double2 *>(lbase + (int64_t)(4 * s) * lld);
           const double2 l0 = pl[0], l1 = pl[1];
@@ -1163,14 +1178,14 @@ __global__ __launch_bounds__(128) void k_nn_wide(int64_t m, int p, int q, const 
         for (; it + 2 <= nit; it += 2) {
           load(a1, b1, at(it + 1));
           __builtin_amdgcn_sched_barrier(0);
-          compute(a0, b0);
+          compute(a0, b0, 16 * it);
           __builtin_amdgcn_sched_barrier(0);
           load(a0, b0, at(it + 2));
           __builtin_amdgcn_sched_barrier(0);
-          compute(a1, b1);
+          compute(a1, b1, 16 * (it + 1));
           __builtin_amdgcn_sched_barrier(0);
         }
-        if (it < nit) compute(a0, b0);
+        if (it < nit) compute(a0, b0, 16 * it);
       }
     } else {
       for (int kk = 0; kk < kend; kk += 16) {
@@ -1183,11 +1198,14 @@ __global__ __launch_bounds__(128) void k_nn_wide(int64_t m, int p, int q, const 
           const double *py = Y + (int64_t)kc * ldy;
           const double *pl = (kc < psplit) ? L + (int64_t)kc * ldl : L2 + (int64_t)(kc - psplit) * ldl2;
 #pragma unroll
-          for (int x = 0; x < NX; ++x) da[s][x] = (kok && yc + x < q) ? py[yc + x] : 0.0;
+          for (int x = 0; x < NX; ++x) {
+            const int col = col_of(x, cl);
+            da[s][x] = (kok && col < q) ? py[col] : 0.0;
+          }
 #pragma unroll
           for (int y = 0; y < 4; ++y) db[s][y] = (kok && rl + y < m) ? pl[rl + y] : 0.0;
         }
-        compute(da, db);
+        compute(da, db, kk);
       }
     }
     if (!SUB) __syncthreads();  // in place: every read of the rows precedes every write
@@ -1195,7 +1213,7 @@ __global__ __launch_bounds__(128) void k_nn_wide(int64_t m, int p, int q, const 
     for (int e = 0; e < 4; ++e)
 #pragma unroll
       for (int x = 0; x < NX; ++x) {
-        const int col = c0 + NX * (g + 4 * e) + x;
+        const int col = col_of(x, g + 4 * e);
         if (col < q) {
           double *pc = C + (int64_t)col * ldc + rl;
           double *pc2 = C2 ? C2 + (int64_t)col * ldc2 + rl : nullptr;
@@ -1220,7 +1238,7 @@ __global__ __launch_bounds__(128) void k_nn_wide(int64_t m, int p, int q, const 
       }
   };
   if ((r0 + 64 <= m) && (kend % 16 == 0) && (psplit % 16 == 0) &&
-      ((q % NX) == 0 || c0 + kCols <= q))
+      (((q % NX) == 0 && !LFIRST) || c0 + kCols <= q))
     body(std::true_type{});
   else
     body(std::false_type{});
@@ -1474,7 +1492,7 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
                      double *C, int64_t ldc, const int *info, hipStream_t s, const double *L2,
                      int64_t ldl2, int psplit, int batch, int64_t sL, int64_t sL2, int64_t sY,
                      int64_t sCin, int64_t sC, double *C2, int64_t ldc2, const int *skip,
-                     int tile) {
+                     int tile, bool lower_first) {
   if (C2 && (subtract || batch != 1)) return hipErrorInvalidValue;
   if (!L2) {
     L2 = L;
@@ -1503,9 +1521,15 @@ hipError_t launch_nn(bool subtract, bool upper_y, int64_t m, int p, int q, const
     // 64 x 128 tile, the accumulators held over the whole inner dimension
     const int nct = (q + 127) / 128;
     const int64_t rts = (m + 63) / 64;
-    hipLaunchKernelGGL((k_nn_wide<8, false, false>), dim3((unsigned)(rts * nct), (unsigned)batch),
-                       dim3(64), 0, s, m, p, q, L, ldl, Y, ldy, nullptr, 0, C, ldc, nct, nullptr, 0,
-                       info, skip, L2, ldl2, psplit, sL, sL2, sY, sC);
+    if (lower_first)
+      hipLaunchKernelGGL((k_nn_wide<8, false, false, true>),
+                         dim3((unsigned)(rts * nct), (unsigned)batch), dim3(64), 0, s, m, p, q, L,
+                         ldl, Y, ldy, nullptr, 0, C, ldc, nct, nullptr, 0, info, skip, L2, ldl2,
+                         psplit, sL, sL2, sY, sC);
+    else
+      hipLaunchKernelGGL((k_nn_wide<8, false, false>), dim3((unsigned)(rts * nct), (unsigned)batch),
+                         dim3(64), 0, s, m, p, q, L, ldl, Y, ldy, nullptr, 0, C, ldc, nct, nullptr,
+                         0, info, skip, L2, ldl2, psplit, sL, sL2, sY, sC);
     return hipGetLastError();
   }
   if (!subtract && !upper_y && C2 == nullptr && p <= kYsMaxK && p % 16 == 0 && psplit % 16 == 0 &&

@@ -1000,12 +1000,17 @@ int cqr_plan_batched(int64_t batch, const int64_t *h_m, const int64_t *h_n, cons
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return CQR_ERR_HIP;
   const int64_t resident = std::max<int64_t>(1, (int64_t)cus * cqr::batched_blocks_per_cu());
-  // Teams: a matrix whose work (~ m n^2) exceeds a resident workgroup's fair
-  // share is split by rows over up to kBatchMaxTeam workgroups (at least
-  // 2048 rows each), so that no single matrix sets the makespan.
+  // Teams: a matrix whose work exceeds a resident workgroup's fair share is
+  // split by rows over up to kBatchMaxTeam workgroups (at least 2048 rows
+  // each), so that no single matrix sets the makespan. The kernel streams
+  // its matrices from memory, so work is priced by the bytes it moves (~ m n
+  // (1 + n / b)) plus a per-panel fixed cost (the n / b small Cholesky steps
+  // and workgroup barriers, about 2048 n rows' worth each), not by flops.
   std::vector<double> work(batch);
   double total = 0;
-  for (int64_t i = 0; i < batch; ++i) total += (work[i] = (double)m[i] * n[i] * n[i]);
+  for (int64_t i = 0; i < batch; ++i)
+    total += (work[i] = (double)m[i] * n[i] * (1.0 + (double)n[i] / b[i]) +
+                        2048.0 * n[i] * n[i] / b[i]);
   const double share = total / (double)std::min<int64_t>(batch, resident);
   std::vector<int> team(batch, 1);
   for (int64_t i = 0; i < batch; ++i) {

@@ -221,13 +221,17 @@ int64_t cqr_default_panel(int64_t m, int64_t n, int schedule);
 
 /* Batched factorisation: many independent matrices of uneven shape in one
  * persistent launch. Each workgroup takes the next work item from a queue
- * ordered longest-first (work ~ m n^2) and runs mCQR2GS (Algorithm 9) on it,
- * with its panel reductions over rows finished in the workgroup's local
- * memory. A matrix whose work exceeds one workgroup's fair share is split by
- * rows over a team of up to four workgroups that add their row-reduced
- * products in a fixed member order through device memory (the paper's
- * distributed form, Algorithm 8, with workgroups for ranks); every member
- * repeats the small Cholesky steps. All workgroups of the launch are
+ * ordered longest-first (work ~ the bytes a matrix moves, m n (1 + n / b))
+ * and runs mCQR2GS (Algorithm 9) on it, with its panel reductions over rows
+ * finished in the workgroup's local memory. A matrix whose work exceeds one
+ * workgroup's fair share is split by rows over a team of up to four
+ * workgroups (at least 2048 rows each); in a batch of at most one matrix
+ * per eight resident workgroups every matrix is split over up to sixteen
+ * (at least 128 rows each), so that a few matrices still fill the device.
+ * Team members add their row-reduced products in a fixed member order
+ * through device memory (the paper's distributed form, Algorithm 8, with
+ * workgroups for ranks); every member repeats the small Cholesky steps.
+ * All workgroups of the launch are
  * resident at once, so team members always find their partners; a wait
  * that still exceeds a spin limit of a few seconds ends with info = -1.
  *

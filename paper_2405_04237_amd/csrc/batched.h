@@ -8,6 +8,10 @@ namespace cqr {
 constexpr int kBatchMaxPanel = 32;  // panel width limit of the batched form
 constexpr int kBatchMaxN = 128;     // column limit of the batched form
 constexpr int kBatchMaxTeam = 4;    // workgroups that may share one matrix
+// a small batch (at most one matrix per eight resident workgroups) splits
+// each matrix over up to this many workgroups of at least kTeamMinRows rows
+constexpr int kBatchMaxTeamSmall = 16;
+constexpr int kTeamMinRows = 128;
 constexpr int kTeamSlot = kBatchMaxPanel * kBatchMaxN;  // doubles per partial product
 
 // One work item of the persistent kernel: member `member` of the `team`

@@ -112,9 +112,10 @@ def test_batched_workload_shape_sample():
 
 
 def test_batched_teams_breakdown_and_determinism():
-    """Matrices whose work exceeds a workgroup's fair share are split by rows
-    over a team of workgroups (here the 65536 x 128 matrix over four, the
-    60000 x 64 one over two). Every member takes the same Cholesky
+    """Matrices are split by rows over a team of workgroups (a batch of eight
+    on a device of hundreds of workgroups splits every matrix over sixteen
+    workgroups of at least 128 rows; a large batch splits the matrices above
+    a fair share over up to four). Every member takes the same Cholesky
     decisions, so a breakdown column is still reported exactly; team sums go
     through a fixed member order, so two runs agree bit for bit; the results
     meet the oracle bounds."""
@@ -136,7 +137,8 @@ def test_batched_teams_breakdown_and_determinism():
 def test_batched_short_and_square():
     """Matrices far below the workload's 2048 rows: square (m = n = 128 and
     64), m just above n, a ragged panel width, and one narrow matrix, all in
-    one launch (one workgroup each; no row-split team below 4096 rows)."""
+    one launch (one workgroup each below 256 rows; the 1000 x 7 matrix is
+    split over a team of seven 128-row shares)."""
     specs = [(128, 128, 32, 1e6), (200, 100, 25, 1e8), (64, 64, 16, 1e3), (1000, 7, 3, 1e2),
              (130, 128, 32, 1e10)]
     mats = [matgen.test_matrix(m, n, k, seed=900 + i) for i, (m, n, b, k) in enumerate(specs)]

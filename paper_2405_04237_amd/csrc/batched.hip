@@ -303,7 +303,9 @@ __device__ __forceinline__ void wg_tn(int64_t m, int na, int nb, const double *A
 // equal C. Lane maps as in k_nn with two rows per lane: lane (cl, g) holds
 // rows r0 + 2 cl + {0, 1} and columns c0 + NX (g + 4 e) + x of the tile.
 // ---------------------------------------------------------------------------
-template <int NX, bool SUB>
+// NS: the 4-wide k groups of each 16-wide k step that are streamed (2 when
+// p <= 8: the other two hold only k >= p, whose terms are exact zeros).
+template <int NX, bool SUB, int NS = 4>
 __device__ __forceinline__ void nn_run(int64_t m, int p, int q, const double *L, int64_t ldl,
                                        const double *Y, int ldy, const double *Cin, int64_t ldci,
                                        double *C, int64_t ldc) {
@@ -330,7 +332,7 @@ __device__ __forceinline__ void nn_run(int64_t m, int p, int q, const double *L,
   };
   auto load_l = [&](double (&l)[4][2], int64_t rl, int ks, int64_t rows_left) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < NS; ++s) {
       const int k = 16 * ks + 4 * s + g;
       const double *pl = L + (int64_t)(k < p ? k : p - 1) * ldl + rl;
       double x0, x1;
@@ -373,7 +375,7 @@ __device__ __forceinline__ void nn_run(int64_t m, int p, int q, const double *L,
   auto mma = [&](const double (&l)[4][2], int ks, int c0) {
     const double *yl = Y + c0 + NX * cl;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < NS; ++s) {
       const int k = 16 * ks + 4 * s + g;
       double ya[NX];
 #pragma unroll
@@ -510,6 +512,13 @@ template <int NX>
 __device__ __forceinline__ void nn_sub(int64_t m, int p, int q, const double *L, int64_t ldl,
                                        const double *Y, int ldy, const double *Cin, int64_t ldci,
                                        double *C, int64_t ldc, bool sub) {
+  if (NX == 1 && p <= 8) {  // an 8-column panel: half of each k step
+    if (sub)
+      nn_run<NX, true, 2>(m, p, q, L, ldl, Y, ldy, Cin, ldci, C, ldc);
+    else
+      nn_run<NX, false, 2>(m, p, q, L, ldl, Y, ldy, Cin, ldci, C, ldc);
+    return;
+  }
   if (sub)
     nn_run<NX, true>(m, p, q, L, ldl, Y, ldy, Cin, ldci, C, ldc);
   else
@@ -662,7 +671,8 @@ __device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int n, int b, const doub
         if (lead) wg_r_upper_product(R, n, 0, w, S.ub, S.ua);
         next = true;
         break;
-      // panel s >= b: Y := Q_{j-1}^T A_{:,j:k}; R_{j-1,j:k} := Y; A_{:,j:k} -= Q_{j-1} Y
+      // panel s >= b: project the finished panel (columns ps..s-1 of Q) out
+      // of every column to its right; the projection is that block row of R
       case 7:
         op = 1; ta = b; tb = nr; tA = Q + (int64_t)ps * lda; tB = (ps == 0) ? A + (int64_t)s * lda : Xj;
         tout = S.y; tldo = (int)padded_ld(nr);
@@ -681,14 +691,16 @@ __device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int n, int b, const doub
         op = 2; np = b; nq = nr; nL = Q + (int64_t)ps * lda; nY = S.y; nldy = (int)padded_ld(nr);
         nCin = (ps == 0) ? A + (int64_t)s * lda : Xj; nC = Xj; nsub = true;
         break;
-      // CQR of panel j: A_j = Qt Ua
+      // first CholeskyQR of the new panel (factor Ua)
       case 10: op = 1; ta = tb = w; tA = tB = Xj; tout = S.w; tldo = w; break;
       case 11: { const int f = wg_chol_inv(S, w, S.ua, ldw); if (f) return s + f; break; }
       case 12: op = 2; np = nq = w; nL = Xj; nY = S.ui; nldy = ldw; nC = Xj; break;
-      // re-orthogonalise: Z := Q_{1:j-1}^T Qt (computed as Qt^T Q_{1:j-1}, stored transposed)
+      // one Gram-Schmidt pass of the new panel against all finished columns
+      // (the coefficients as Qt^T Q_{1:j-1}, stored transposed)
       case 13: op = 1; ta = w; tb = s; tA = Xj; tB = Q; tout = S.y; tldo = ldw; ttrans = true; break;
       case 14: {
-        // R_{1:j-1,j} += Z Ua; then Y := -Z for the update
+        // the coefficients times Ua add into R's block above the panel; the
+        // update then subtracts Q_{1:j-1} times the coefficients
         for (int e = tid; lead && e < s * w; e += kThreads) {
           const int i = e % s, c = e / s;
           double acc = 0.0;
@@ -702,7 +714,7 @@ __device__ __forceinline__ int wg_mcqr2gs(const Lds &S, int n, int b, const doub
         break;
       }
       case 15: op = 2; np = s; nq = w; nL = Q; nY = S.y; nldy = ldw; nCin = Xj; nC = Xj; nsub = true; break;
-      // CQR again: Qt = Q_j Ub; R_jj = Ub Ua
+      // second CholeskyQR of the panel (factor Ub); its R block is Ub Ua
       case 16: op = 1; ta = tb = w; tA = tB = Xj; tout = S.w; tldo = w; break;
       case 17: { const int f = wg_chol_inv(S, w, S.ub, ldw); if (f) return s + f; break; }
       case 18: op = 2; np = nq = w; nL = Xj; nY = S.ui; nldy = ldw; nC = Xj; break;

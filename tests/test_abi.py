@@ -128,6 +128,9 @@ def test_batched_plan_argument_errors(lib):
     with pytest.raises(_lib.CqrError) as e:
         _lib.plan_batched([1000], [100], [-1], _lib.SCHED_MOD)
     assert e.value.status == _lib.CQR_ERR_ARG
+    with pytest.raises(_lib.CqrError) as e:
+        _lib.plan_batched([(1 << 33) + 1], [16], None, _lib.SCHED_MOD)  # rows past 2^33
+    assert e.value.status == _lib.CQR_ERR_UNSUPPORTED
     assert _lib.lib().cqr_factor_batched(None, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.CQR_ERR_ARG
 
 

@@ -147,3 +147,25 @@ def test_batched_short_and_square():
     assert not info.any()
     for a, q, r, (m, n, b, k) in zip(mats, qs, rs, specs):
         _check(a, to_host(q), to_host(r), b, k)
+
+
+def test_batched_single_small_matrix_team():
+    """One small matrix in a launch of hundreds of resident workgroups is
+    split over a team of up to sixteen 128-row-or-larger shares (the
+    latency form of the batched kernel): it meets the oracle bounds, two
+    runs agree bit for bit, and a zero column is reported at its index."""
+    m, n, b, kappa = 4096, 64, 16, 1e12
+    a = matgen.test_matrix(m, n, kappa, seed=950)
+    runs = []
+    for _ in range(2):
+        qs, rs, info = cqr.qr_batched([to_dev(a)], bs=[b])
+        torch.cuda.synchronize()
+        assert not info.any()
+        runs.append((to_host(qs[0]), to_host(rs[0])))
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    _check(a, runs[0][0], runs[0][1], b, kappa)
+    z = np.array(a, copy=True)
+    z[:, 40] = 0.0
+    _, _, info = cqr.qr_batched([to_dev(z)], bs=[b], check=False)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [41]

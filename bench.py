@@ -64,10 +64,11 @@ def traffic_for(kind: str, workload: str):
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
-def bench_batched(steps: int, warmup: int):
+def bench_batched(steps: int, warmup: int, tune_widths: bool = True):
     """The batched workload (512 matrices of uneven shape) in one persistent
     launch, captured in a HIP graph and replayed; inputs generated on the host
-    (the recipe of matgen.batch_problems) and uploaded before timing."""
+    (the recipe of matgen.batch_problems) and uploaded before timing.
+    tune_widths = False keeps the default panel widths (profiler runs)."""
     import numpy as np
     import torch
     import matgen
@@ -80,7 +81,10 @@ def bench_batched(steps: int, warmup: int):
         a = matgen.test_matrix(p.m, p.n, p.kappa, p.seed)
         mats.append(torch.from_numpy(np.ascontiguousarray(a.T)).to("cuda").t())
     from paper_2405_04237_amd import tune
-    bs, tune_table = tune.tune_batched(mats, [p.b for p in probs], log=log)
+    if tune_widths:
+        bs, tune_table = tune.tune_batched(mats, [p.b for p in probs], log=log)
+    else:
+        bs, tune_table = [p.b for p in probs], None
     chosen = {n: sorted({b for b, p in zip(bs, probs) if p.n == n}) for n in sorted({p.n for p in probs})}
     log(f"batched: panel widths per column count {chosen}")
     call = cqr.BatchedCall(mats, bs=bs)
@@ -536,6 +540,9 @@ def main():
                     help="finish with one 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-staged", action="store_true",
                     help="skip the extra timing of the same matrix with lda = m")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="time only the batched workload (its graph replay) and print its "
+                         "JSON; with --no-tile-tune its panel widths are the defaults")
     ap.add_argument("--lda-pad", type=int, default=16,
                     help="store A and Q with leading dimension m + pad (0: lda = m, which "
                          "for m = 2^22 aliases cache sets and makes the library factor a "
@@ -557,6 +564,16 @@ def main():
         sys.exit(3)
     _lib.lib()  # fail loudly if libcqr.so is missing
     dev = torch.device("cuda:0")
+    if args.batched_only:
+        out = {"batched": bench_batched(args.steps, args.warmup, tune_widths=not args.no_tile_tune)}
+        if args.calibration_copy:
+            x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+            y = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+            x.copy_(y)
+            torch.cuda.synchronize()
+            out["calibration_copy_bytes"] = 2 * 8 * (1 << 27)
+        print(json.dumps(out), flush=True)
+        return
     w = WORKLOADS[args.workload]
     m, n, kappa = w["m"], w["n"], w["kappa"]
     t0 = time.perf_counter()

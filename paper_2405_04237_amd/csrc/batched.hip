@@ -77,12 +77,15 @@ __device__ __forceinline__ void gst2(double *p, double2 v) {
 }
 
 // Global-memory writes made by one wave before the barrier are visible to
-// every wave of the workgroup after it: release fence, barrier, then an
-// acquire fence that drops stale vector-L1 lines (agent scope on both sides).
+// every wave of the workgroup after it. All waves of a workgroup run on one
+// compute unit and share its vector L1, so workgroup-scope release and
+// acquire (the barrier's own fences) suffice: agent scope would write back
+// and invalidate the L2 at every phase. Exchanges between the workgroups of
+// a team use agent-scope fences of their own (team_reduce).
 __device__ inline void wg_sync() {
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __syncthreads();
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // ---------------------------------------------------------------------------

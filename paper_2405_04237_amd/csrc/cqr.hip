@@ -1011,7 +1011,9 @@ int cqr_plan_batched(int64_t batch, const int64_t *h_m, const int64_t *h_n, cons
   for (int64_t i = 0; i < batch; ++i)
     total += (work[i] = (double)m[i] * n[i] * (1.0 + (double)n[i] / b[i]) +
                         2048.0 * n[i] * n[i] / b[i]);
-  const double share = total / (double)std::min<int64_t>(batch, resident);
+  // (the share is taken over every resident workgroup, so a batch of fewer
+  // matrices than workgroups still splits its largest matrices)
+  const double share = total / (double)resident;
   // A batch of at most one matrix per eight resident workgroups is a latency
   // problem rather than a throughput one: every matrix is split over as many
   // row shares of at least kTeamMinRows rows as the idle workgroups allow
